@@ -1,0 +1,222 @@
+/*
+ * svdlut.h — C ABI of the MI355X (gfx950) hot path of the SVD-decomposed, spatially
+ * weighted 2D lookup-table image enhancer (Kim, Lee & Cho, arXiv 2508.16121).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  * Pointers named x, y, U, s, V, map, T, bias, dx, dy, dU, ds, dV, dmap, dbias, params,
+ *    grads, m, v, ws are DEVICE pointers owned by the caller.  The library never frees
+ *    or retains them past the call.  Descriptor arrays passed as "host" are read during
+ *    the call only.
+ *  * Every call is asynchronous on the given hipStream_t (NULL = the legacy default
+ *    stream) and returns a status.  Arguments are validated before any HIP call; a
+ *    rejected call returns SVDLUT_EINVAL (or SVDLUT_EUNSUPPORTED) and enqueues nothing.
+ *    A launch failure returns SVDLUT_EDEVICE.  svdlut_last_error() gives a message for
+ *    the calling thread's most recent failure.  Faults inside kernels surface at the
+ *    caller's next synchronisation.
+ *  * Channels a in {0: r, 1: g, 2: b}.  Colour pairs p in {0: rg, 1: rb, 2: gb} with
+ *    (alpha, beta) = (0,1), (0,2), (1,2).  The nine LUTs of an image, and the nine
+ *    channels of its spatial map, are indexed l = 3*c + p for output channel c.
+ *  * Images are planar: [3][H][W] per image, batches [B][3][H][W], row-major.
+ *    Factors: U, V [B][9][D][R] and s [B][9][R], float32.  A LUT is indexed
+ *    T_l[i][j] with row i along the pair's first channel (alpha) and column j along its
+ *    second (beta): T_l = U_l diag(s_l) V_l^T.  Spatial map [B][9][h][w].
+ *  * Gradients are overwritten, never accumulated.
+ *  * Limits: 2 <= D <= 40 (the LUTs and their gradients are staged in LDS), 1 <= R <= 64,
+ *    1 <= H, W, h, w <= 65535, B >= 1.
+ */
+#ifndef SVDLUT_H
+#define SVDLUT_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SVDLUT_OK = 0,
+    SVDLUT_EINVAL = 1,        /* bad pointer, size or dimension */
+    SVDLUT_EUNSUPPORTED = 2,  /* dtype or configuration not supported */
+    SVDLUT_ENOMEM = 3,        /* an explicit plan could not allocate its device tables */
+    SVDLUT_EDEVICE = 4        /* a HIP call or kernel launch failed */
+} svdlut_status;
+
+typedef enum { SVDLUT_F32 = 0, SVDLUT_F16 = 1 } svdlut_dtype;
+
+typedef enum { SVDLUT_LOSS_L1 = 0, SVDLUT_LOSS_MSE = 1 } svdlut_loss_kind;
+
+/* Message for the calling thread's most recent failed call ("" if none). */
+const char* svdlut_last_error(void);
+/* Library version string. */
+const char* svdlut_version(void);
+
+/*
+ * svdlut_reconstruct — 2D LUTs from their rank-R factors (Sec. "Singular Value
+ * Decomposition", Eq. gen_LUT_SVD: T = U . S . V^T with S = diag(s)).
+ *   U, V: [n_luts][D][R] float32; s: [n_luts][R]; T (out): [n_luts][D][D] float32,
+ *   T[n][i][j] = sum_k U[n][i][k] * s[n][k] * V[n][j][k].
+ */
+svdlut_status svdlut_reconstruct(const float* U, const float* s, const float* V, float* T,
+                                 int32_t n_luts, int32_t D, int32_t R, hipStream_t stream);
+
+/*
+ * svdlut_apply — spatially weighted 2D-LUT transform of a batch of same-size images, with
+ * the LUT reconstruction fused into the launch (each workgroup rebuilds its image's nine
+ * LUTs into LDS).  Follows the 2D LUT transform of the supplementary material (Eqs.
+ * query_lut, lookup, adjacent, bilinear, weighte_sum) with the scalar LUT weights replaced
+ * by a per-pixel weight: Y_c = sum_p S_{3c+p}(y, x) * phi_{3c+p} + bias_c, where
+ *   phi_l  = bilinear lookup of T_l at (p_alpha, p_beta), p = min(max(X, 0), 1) (NaN -> 0);
+ *            cell i = min(floor(q), D-2) with q = p*(D-1) rounded to float32, delta = q - i;
+ *   S_l    = corner-aligned bilinear upsample of map channel l (x' = x/(W-1), y' = y/(H-1);
+ *            a size-1 map axis is constant).
+ *   x:    [B][3][H][W], dtype io (F32 or F16 storage; arithmetic is float32)
+ *   y:    [B][3][H][W] (out), dtype io; F16 output is rounded to nearest even.  No clamp.
+ *   map:  [B][9][h][w], dtype map_dt
+ *   bias: [B][3] float32 or NULL (= 0)
+ */
+svdlut_status svdlut_apply(const void* x, void* y, svdlut_dtype io,
+                           const float* U, const float* s, const float* V,
+                           const void* map, svdlut_dtype map_dt, const float* bias,
+                           int32_t B, int32_t H, int32_t W, int32_t h, int32_t w,
+                           int32_t D, int32_t R, hipStream_t stream);
+
+/*
+ * svdlut_apply_bwd — gradients of a scalar loss through svdlut_apply, given
+ * dy = dL/dY [B][3][H][W] (dtype io).  By the chain rule of the forward:
+ *   dT_l[i_a + a][i_b + b] += dy_c * S_l * w_alpha(a) * w_beta(b)   (then dU, ds, dV below)
+ *   dmap_l[iv + a][iu + b] += dy_c * phi_l * wv(a) * wu(b)
+ *   dx_a = sum over the two pairs containing a of dy_c * S_l * dphi_l/dp_a, times 1 where
+ *          0 <= x_a <= 1 and 0 elsewhere (and for NaN)
+ *   dbias_c = sum of dy_c over the image
+ *   dU = dT V diag(s), dV = dT^T U diag(s), ds_k = sum_ij dT_ij U_ik V_jk.
+ * Outputs (each may be NULL to skip it; dU, ds and dV are all NULL or all set):
+ *   dx [B][3][H][W] dtype io; dU, dV [B][9][D][R]; ds [B][9][R]; dmap [B][9][h][w]
+ *   float32; dbias [B][3] float32.
+ * ws: device workspace of at least svdlut_apply_bwd_workspace_size(B, D) bytes, 256-byte
+ *   aligned, owned by the caller; contents on entry are ignored.
+ * Float atomics make dU, ds, dV, dmap and dbias depend on summation order at the level
+ * of float32 rounding; dx is deterministic.
+ */
+size_t svdlut_apply_bwd_workspace_size(int32_t B, int32_t D);
+svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io,
+                               const float* U, const float* s, const float* V,
+                               const void* map, svdlut_dtype map_dt,
+                               void* dx, float* dU, float* ds, float* dV,
+                               float* dmap, float* dbias,
+                               int32_t B, int32_t H, int32_t W, int32_t h, int32_t w,
+                               int32_t D, int32_t R, void* ws, size_t ws_bytes,
+                               hipStream_t stream);
+
+/*
+ * Batches of images of uneven size.  Image b of a batch lives in packed planar buffers at
+ * the element offsets of its descriptor: x + x_off holds its [3][H][W] planes, y + y_off
+ * receives them, map + map_off holds its [9][h][w] map.  Factors stay [B][9][D][R].
+ */
+typedef struct {
+    int32_t H, W, h, w;
+    int64_t x_off, y_off, map_off;
+} svdlut_image_desc;
+
+/*
+ * svdlut_plan — one persistent launch over every pixel tile of a batch of uneven images,
+ * captured once into a HIP graph and replayed.  Tiles are ordered image-major so that a
+ * workgroup rebuilds a given image's LUTs at most once.  Creating a plan uploads the
+ * descriptors and the tile prefix table to device memory owned by the plan (the only
+ * allocation on this path) and picks tile and grid shapes from the autotuner's cache
+ * (or the built-in default).  Launching with other buffer addresses than the previous
+ * launch updates the graph's kernel arguments in place before the replay.
+ *   descs: host array of B descriptors; io / map_dt as for svdlut_apply.
+ */
+typedef struct svdlut_plan svdlut_plan;
+
+typedef struct {
+    int64_t pixels;        /* total pixels of the batch */
+    int64_t tiles;         /* work tiles (one row segment each) */
+    int32_t block;         /* threads per workgroup */
+    int32_t grid;          /* workgroups in the persistent launch */
+    int32_t tuned;         /* 1 if the shape came from the autotuner */
+    int32_t graph;         /* 1 if launches replay a captured HIP graph */
+} svdlut_plan_info;
+
+svdlut_status svdlut_plan_create(const svdlut_image_desc* descs, int32_t B, int32_t D, int32_t R,
+                                 svdlut_dtype io, svdlut_dtype map_dt, svdlut_plan** out);
+/* Time each candidate workgroup shape on the given buffers (outputs are overwritten),
+ * keep the fastest, record it in the tuning cache (saved to the JSON file named by the
+ * SVDLUT_TUNE_CACHE environment variable when set), and rebuild the graph. */
+svdlut_status svdlut_plan_autotune(svdlut_plan* plan, const void* x, void* y,
+                                   const float* U, const float* s, const float* V,
+                                   const void* map, const float* bias, hipStream_t stream);
+svdlut_status svdlut_plan_launch(svdlut_plan* plan, const void* x, void* y,
+                                 const float* U, const float* s, const float* V,
+                                 const void* map, const float* bias, hipStream_t stream);
+/* The same work as a plan launch, without the graph (a plain kernel launch). */
+svdlut_status svdlut_plan_launch_direct(svdlut_plan* plan, const void* x, void* y,
+                                        const float* U, const float* s, const float* V,
+                                        const void* map, const float* bias, hipStream_t stream);
+svdlut_status svdlut_plan_get_info(const svdlut_plan* plan, svdlut_plan_info* info);
+svdlut_status svdlut_plan_destroy(svdlut_plan* plan);
+
+/*
+ * Loss of an enhanced batch against a target (Sec. "Loss Function": the fidelity term is
+ * the mean squared error; the mean absolute error is also provided).
+ *   y, target: n elements of dtype io.  loss: one float32 (out) = mean |y - t| or
+ *   mean (y - t)^2.  dy (nullable, out, dtype io): dL/dy = sign(y - t)/n (sign(0) = 0) or
+ *   2 (y - t)/n.  ws: at least svdlut_loss_workspace_size(n) bytes.
+ */
+size_t svdlut_loss_workspace_size(int64_t n);
+svdlut_status svdlut_loss(const void* y, const void* target, svdlut_dtype io, int64_t n,
+                          svdlut_loss_kind kind, float* loss, void* dy,
+                          void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * Learned generator of the factors and the spatial map from a downsampled image (the
+ * paper's backbone + LUT generator, Sec. "Preliminary" Eq. backbone and supplementary
+ * Tables backbone / gen_lut, sized as a small CNN):
+ *   bilinear downsample to 256x256 (half-pixel centres, no antialias)
+ *   5 x [conv3x3 stride 2 pad 1 + ReLU]: 3 -> 16 -> 32 -> 64 -> 128 -> 128
+ *   global average pool -> FC 128 -> 9*(D*R + R + D*R): per LUT l the block
+ *     [U_l (D x R row-major) | s_l (R) | V_l (D x R)]
+ *   map head: conv3x3 stride 1 pad 1, 64 -> 9, on the 32x32 third-layer features
+ * Convolutions run on bf16 matrix cores (MFMA) with float32 accumulation; activations are
+ * stored as bf16; pooling, FC, bias and optimiser state are float32.
+ * params: float32 vector of svdlut_generator_param_count(D, R) values, in order
+ *   conv1.w [16][3][3][3], conv1.b [16], conv2.w [32][3][3][16], conv2.b, conv3.w
+ *   [64][3][3][32], conv3.b, conv4.w [128][3][3][64], conv4.b, conv5.w [128][3][3][128],
+ *   conv5.b, head.w [9][3][3][64], head.b [9], fc.w [9*(2DR+R)][128], fc.b
+ *   (convolution weights are [Cout][ky][kx][Cin]).
+ * ws: workspace of svdlut_generator_workspace_size(B, D, R) bytes holding the
+ *   activations of the last forward; svdlut_generator_bwd reads them, so the two calls
+ *   must share ws and the parameters must not change between them.
+ * Forward outputs: U, V [B][9][D][R], s [B][9][R], map [B][9][32][32], float32.
+ * Backward inputs dU, ds, dV, dmap have the same shapes; grads (out) has the layout of
+ * params.
+ */
+size_t svdlut_generator_param_count(int32_t D, int32_t R);
+size_t svdlut_generator_workspace_size(int32_t B, int32_t D, int32_t R);
+svdlut_status svdlut_generator_fwd(const float* params, const void* x, svdlut_dtype io,
+                                   int32_t B, int32_t H, int32_t W, int32_t D, int32_t R,
+                                   float* U, float* s, float* V, float* map,
+                                   void* ws, size_t ws_bytes, hipStream_t stream);
+svdlut_status svdlut_generator_bwd(const float* params, const float* dU, const float* ds,
+                                   const float* dV, const float* dmap, float* grads,
+                                   int32_t B, int32_t D, int32_t R,
+                                   void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
+ * svdlut_adam_step — one step of standard Adam (the paper trains with Adam, Sec.
+ * "Application Settings"), in place on n float32 values:
+ *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;
+ *   p -= lr * (m / (1 - b1^step)) / (sqrt(v / (1 - b2^step)) + eps),   step >= 1.
+ */
+svdlut_status svdlut_adam_step(float* params, const float* grads, float* m, float* v, int64_t n,
+                               float lr, float b1, float b2, float eps, int32_t step,
+                               hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SVDLUT_H */

@@ -138,6 +138,42 @@ def transform(x, T, smap, bias=None):
     return Y
 
 
+def transform_at(x, T, smap, ys, xs, bias=None):
+    """The same transform evaluated only at pixels (ys[k], xs[k]) of an image of size x.shape.
+
+    Uses the image's full-size coordinates for the map upsample, so the values equal the
+    corresponding entries of transform(); for sampled checks of large images.
+    Returns float64 [3][len(ys)].
+    """
+    x = np.asarray(x)
+    T = np.asarray(T, dtype=np.float64)
+    m = np.asarray(smap, dtype=np.float64)
+    _, H, W = x.shape
+    D = T.shape[-1]
+    C, h, w = m.shape
+    ys = np.asarray(ys, np.int64)
+    xs = np.asarray(xs, np.int64)
+    ivs, dvs = axis_coords(H, h)
+    ius, dus = axis_coords(W, w)
+    iv, dv = ivs[ys], dvs[ys]
+    iu, du = ius[xs], dus[xs]
+    iv1 = np.minimum(iv + 1, h - 1)
+    iu1 = np.minimum(iu + 1, w - 1)
+    S = ((1 - dv) * ((1 - du) * m[:, iv, iu] + du * m[:, iv, iu1])
+         + dv * ((1 - du) * m[:, iv1, iu] + du * m[:, iv1, iu1]))
+    px = x[:, ys, xs]
+    dec = [decode(px[a], D) for a in range(3)]
+    Y = np.zeros((3, ys.size))
+    for c in range(3):
+        for p, (al, be) in enumerate(PAIRS):
+            l = lut_id(c, p)
+            (ia, da), (ib, db) = dec[al], dec[be]
+            Y[c] += S[l] * bilinear(T[l], ia, da, ib, db)
+        if bias is not None:
+            Y[c] += float(bias[c])
+    return Y
+
+
 def apply(x, U, s, V, smap, bias=None):
     """Batched forward: x [B][3][H][W], U/V [B][9][D][R], s [B][9][R], smap [B][9][h][w]."""
     T = reconstruct(U, s, V)

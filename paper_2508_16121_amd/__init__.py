@@ -1,0 +1,15 @@
+"""MI355X (gfx950) hot path of the SVD-decomposed spatial-aware 2D-LUT image enhancer.
+
+All computation runs in the HIP library libsvdlut.so (C ABI in include/svdlut.h); this
+package only marshals torch device tensors and the current stream into it.  Importing the
+package loads the library and fails if it has not been built.
+"""
+from ._lib import SvdlutError, load as _load_lib
+
+_load_lib()
+
+from .ops import apply, apply_autograd, apply_bwd, bwd_workspace, loss, reconstruct  # noqa: E402
+from .plan import Plan, pack_offsets  # noqa: E402
+
+__all__ = ["apply", "apply_autograd", "apply_bwd", "bwd_workspace", "loss", "reconstruct", "Plan",
+           "pack_offsets", "SvdlutError"]

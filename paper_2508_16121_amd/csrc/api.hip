@@ -1,0 +1,522 @@
+// extern "C" entry points of the 2D-LUT path: argument validation (before any HIP call),
+// launch configuration, error reporting, and the uneven-batch plan (HIP graph + tuner).
+#include "internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <map>
+#include <mutex>
+#include <sstream>
+#include <vector>
+
+namespace svdlut {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+svdlut_status fail(svdlut_status st, const std::string& msg) {
+    set_error(msg);
+    return st;
+}
+
+svdlut_status check_launch(const char* what) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        return fail(SVDLUT_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return SVDLUT_OK;
+}
+
+const DeviceInfo& device_info() {
+    static std::mutex mu;
+    static std::map<int, DeviceInfo> cache;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(dev);
+    if (it != cache.end()) return it->second;
+    DeviceInfo d;
+    d.device = dev;
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && v > 0) d.cus = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess && v > 0)
+        d.lds_per_block = v;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) == hipSuccess && v > 0)
+        d.lds_per_cu = v;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) == hipSuccess) d.arch = prop.gcnArchName;
+    (void)hipGetLastError();
+    return cache.emplace(dev, d).first->second;
+}
+
+size_t bwd_workspace_bytes(int B, int D);
+
+// ---------------------------------------------------------------- validation helpers
+static bool dims_ok(int64_t v) { return v >= 1 && v <= kMaxDim; }
+
+static svdlut_status check_lut_dims(int D, int R) {
+    if (D < 2 || D > kMaxD) return fail(SVDLUT_EINVAL, "D must be in [2, 40]");
+    if (R < 1 || R > kMaxR) return fail(SVDLUT_EINVAL, "R must be in [1, 64]");
+    return SVDLUT_OK;
+}
+
+static svdlut_status check_dtype(svdlut_dtype t, const char* what) {
+    if (t != SVDLUT_F32 && t != SVDLUT_F16)
+        return fail(SVDLUT_EUNSUPPORTED, std::string(what) + ": dtype must be SVDLUT_F32 or SVDLUT_F16");
+    return SVDLUT_OK;
+}
+
+#define SVDLUT_TRY(expr)                          \
+    do {                                          \
+        const svdlut_status st_ = (expr);         \
+        if (st_ != SVDLUT_OK) return st_;         \
+    } while (0)
+
+// Default launch shape of the fused apply: largest block whose LDS fits two workgroups per CU.
+static int default_block(int D, int R, int ncol_max, const DeviceInfo& di) {
+    const int cands[3] = {512, 1024, 256};
+    for (int b : cands) {
+        const size_t lds = apply_lds_bytes(D, R, b, ncol_max);
+        if (lds <= static_cast<size_t>(di.lds_per_block) && 2 * lds <= static_cast<size_t>(di.lds_per_cu))
+            return b;
+    }
+    for (int b : {256, 128, 64})
+        if (apply_lds_bytes(D, R, b, ncol_max) <= static_cast<size_t>(di.lds_per_block)) return b;
+    return 0;
+}
+
+static int blocks_per_cu(int D, int R, int block, int ncol_max, const DeviceInfo& di) {
+    const size_t lds = apply_lds_bytes(D, R, block, ncol_max);
+    int by_lds = static_cast<int>(di.lds_per_cu / std::max<size_t>(lds, 1));
+    int by_waves = 32 / std::max(block / kWave, 1);
+    return std::max(1, std::min(by_lds, by_waves));
+}
+
+}  // namespace svdlut
+
+using namespace svdlut;
+
+// ================================================================== C ABI
+extern "C" {
+
+const char* svdlut_last_error(void) { return g_last_error.c_str(); }
+
+const char* svdlut_version(void) { return "svdlut-mi355x 0.1 (gfx950)"; }
+
+svdlut_status svdlut_reconstruct(const float* U, const float* s, const float* V, float* T,
+                                 int32_t n_luts, int32_t D, int32_t R, hipStream_t stream) {
+    if (!U || !s || !V || !T) return fail(SVDLUT_EINVAL, "reconstruct: null pointer");
+    if (n_luts < 1) return fail(SVDLUT_EINVAL, "reconstruct: n_luts must be >= 1");
+    SVDLUT_TRY(check_lut_dims(D, R));
+    return launch_reconstruct(U, s, V, T, n_luts, D, R, stream);
+}
+
+svdlut_status svdlut_apply(const void* x, void* y, svdlut_dtype io, const float* U, const float* s,
+                           const float* V, const void* map, svdlut_dtype map_dt, const float* bias,
+                           int32_t B, int32_t H, int32_t W, int32_t h, int32_t w, int32_t D,
+                           int32_t R, hipStream_t stream) {
+    if (!x || !y || !U || !s || !V || !map) return fail(SVDLUT_EINVAL, "apply: null pointer");
+    SVDLUT_TRY(check_dtype(io, "apply io"));
+    SVDLUT_TRY(check_dtype(map_dt, "apply map"));
+    if (B < 1) return fail(SVDLUT_EINVAL, "apply: B must be >= 1");
+    if (!dims_ok(H) || !dims_ok(W) || !dims_ok(h) || !dims_ok(w))
+        return fail(SVDLUT_EINVAL, "apply: H, W, h, w must be in [1, 65535]");
+    SVDLUT_TRY(check_lut_dims(D, R));
+    const DeviceInfo& di = device_info();
+    ApplyLaunch a{};
+    a.x = x; a.y = y; a.U = U; a.s = s; a.V = V; a.map = map; a.bias = bias;
+    a.B = B; a.D = D; a.R = R; a.H = H; a.W = W; a.h = h; a.w = w;
+    a.descs = nullptr; a.tile_start = nullptr;
+    a.total_tiles = static_cast<int64_t>(B) * H * ((W + kSeg - 1) / kSeg);
+    a.ncol_max = map_cols_bound(W, w);
+    a.fast_map = map_fast_ok(W, w) ? 1 : 0;
+    a.block = default_block(D, R, a.ncol_max, di);
+    if (a.block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply: map too wide for LDS staging");
+    const int64_t max_grid = static_cast<int64_t>(di.cus) * blocks_per_cu(D, R, a.block, a.ncol_max, di);
+    const int64_t tiles_per_block_min = a.block / kWave;   // at least one tile per wave
+    a.grid = static_cast<int>(std::max<int64_t>(1, std::min(max_grid, (a.total_tiles + tiles_per_block_min - 1) / tiles_per_block_min)));
+    a.io = io; a.map_dt = map_dt;
+    return launch_apply(a, stream);
+}
+
+size_t svdlut_apply_bwd_workspace_size(int32_t B, int32_t D) {
+    if (B < 1 || D < 2 || D > kMaxD) return 0;
+    return bwd_workspace_bytes(B, D);
+}
+
+svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io, const float* U,
+                               const float* s, const float* V, const void* map, svdlut_dtype map_dt,
+                               void* dx, float* dU, float* ds, float* dV, float* dmap, float* dbias,
+                               int32_t B, int32_t H, int32_t W, int32_t h, int32_t w, int32_t D,
+                               int32_t R, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!x || !dy || !U || !s || !V || !map) return fail(SVDLUT_EINVAL, "apply_bwd: null input pointer");
+    const int nfac = (dU != nullptr) + (ds != nullptr) + (dV != nullptr);
+    if (nfac != 0 && nfac != 3) return fail(SVDLUT_EINVAL, "apply_bwd: dU, ds, dV must be all set or all NULL");
+    SVDLUT_TRY(check_dtype(io, "apply_bwd io"));
+    SVDLUT_TRY(check_dtype(map_dt, "apply_bwd map"));
+    if (B < 1) return fail(SVDLUT_EINVAL, "apply_bwd: B must be >= 1");
+    if (!dims_ok(H) || !dims_ok(W) || !dims_ok(h) || !dims_ok(w))
+        return fail(SVDLUT_EINVAL, "apply_bwd: H, W, h, w must be in [1, 65535]");
+    SVDLUT_TRY(check_lut_dims(D, R));
+    if (nfac == 3) {
+        if (!ws) return fail(SVDLUT_EINVAL, "apply_bwd: workspace required for dU, ds, dV");
+        if (ws_bytes < bwd_workspace_bytes(B, D))
+            return fail(SVDLUT_EINVAL, "apply_bwd: workspace smaller than svdlut_apply_bwd_workspace_size()");
+    }
+    if (!dx && nfac == 0 && !dmap && !dbias) return SVDLUT_OK;
+    BwdLaunch a{};
+    a.x = x; a.dy = dy; a.U = U; a.s = s; a.V = V; a.map = map;
+    a.dx = dx; a.dU = dU; a.ds = ds; a.dV = dV; a.dmap = dmap; a.dbias = dbias;
+    a.dT = static_cast<float*>(ws);
+    a.B = B; a.H = H; a.W = W; a.h = h; a.w = w; a.D = D; a.R = R;
+    a.io = io; a.map_dt = map_dt;
+    return launch_apply_bwd(a, stream);
+}
+
+}  // extern "C"
+
+// ================================================================== uneven-batch plan
+struct svdlut_plan {
+    int B = 0, D = 0, R = 0;
+    svdlut_dtype io = SVDLUT_F32, map_dt = SVDLUT_F32;
+    std::vector<ImgGeom> descs;
+    std::vector<int64_t> tile_start;      // B+1
+    int64_t pixels = 0, tiles = 0;
+    int ncol_max = 1;
+    int fast_map = 1;
+    int block = 512, grid = 1;
+    int tuned = 0;
+    ImgGeom* d_descs = nullptr;
+    int64_t* d_tiles = nullptr;
+    int device = 0;
+    // graph state
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipGraphNode_t node = nullptr;
+    ApplyLaunch captured{};
+    bool have_graph = false;
+};
+
+namespace svdlut {
+
+static std::mutex g_tune_mu;
+static std::map<std::string, std::pair<int, int>> g_tune;   // key -> (block, blocks per CU)
+static bool g_tune_loaded = false;
+
+static std::string tune_key(const svdlut_plan* p, const DeviceInfo& di) {
+    // size class: log2 of the pixel count, and whether every map is coarse enough for FASTMAP
+    int lg = 0;
+    for (int64_t v = std::max<int64_t>(p->pixels, 1); v > 1; v >>= 1) ++lg;
+    std::ostringstream os;
+    os << (di.arch.empty() ? "gfx" : di.arch.substr(0, di.arch.find(':'))) << "|io" << p->io << "|map"
+       << p->map_dt << "|D" << p->D << "|R" << p->R << "|px2^" << lg << "|fast" << p->fast_map;
+    return os.str();
+}
+
+// The cache file is a flat JSON object {"key": [block, blocks_per_cu], ...}.
+static void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = std::getenv("SVDLUT_TUNE_CACHE");
+    if (!path) return;
+    std::ifstream f(path);
+    if (!f) return;
+    std::stringstream ss;
+    ss << f.rdbuf();
+    const std::string txt = ss.str();
+    size_t pos = 0;
+    while (true) {
+        const size_t k0 = txt.find('"', pos);
+        if (k0 == std::string::npos) break;
+        const size_t k1 = txt.find('"', k0 + 1);
+        if (k1 == std::string::npos) break;
+        const size_t b0 = txt.find('[', k1);
+        const size_t b1 = txt.find(']', b0 == std::string::npos ? k1 : b0);
+        if (b0 == std::string::npos || b1 == std::string::npos) break;
+        int blk = 0, bpc = 0;
+        if (std::sscanf(txt.c_str() + b0, "[%d , %d]", &blk, &bpc) == 2 ||
+            std::sscanf(txt.c_str() + b0, "[%d,%d]", &blk, &bpc) == 2) {
+            if ((blk == 64 || blk == 128 || blk == 256 || blk == 512 || blk == 1024) && bpc >= 1 && bpc <= 32)
+                g_tune[txt.substr(k0 + 1, k1 - k0 - 1)] = {blk, bpc};
+        }
+        pos = b1 + 1;
+    }
+}
+
+static void tune_save_locked() {
+    const char* path = std::getenv("SVDLUT_TUNE_CACHE");
+    if (!path) return;
+    std::ofstream f(path);
+    if (!f) return;
+    f << "{\n";
+    size_t i = 0;
+    for (const auto& kv : g_tune) {
+        f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
+          << (++i < g_tune.size() ? "," : "") << "\n";
+    }
+    f << "}\n";
+}
+
+static ApplyLaunch plan_args(const svdlut_plan* p, const void* x, void* y, const float* U, const float* s,
+                             const float* V, const void* map, const float* bias) {
+    ApplyLaunch a{};
+    a.x = x; a.y = y; a.U = U; a.s = s; a.V = V; a.map = map; a.bias = bias;
+    a.B = p->B; a.D = p->D; a.R = p->R;
+    a.H = a.W = a.h = a.w = 0;
+    a.descs = p->d_descs; a.tile_start = p->d_tiles;
+    a.total_tiles = p->tiles;
+    a.ncol_max = p->ncol_max; a.fast_map = p->fast_map;
+    a.block = p->block; a.grid = p->grid;
+    a.io = p->io; a.map_dt = p->map_dt;
+    return a;
+}
+
+static void plan_drop_graph(svdlut_plan* p) {
+    if (p->exec) (void)hipGraphExecDestroy(p->exec);
+    if (p->graph) (void)hipGraphDestroy(p->graph);
+    p->exec = nullptr; p->graph = nullptr; p->node = nullptr; p->have_graph = false;
+}
+
+static svdlut_status plan_capture(svdlut_plan* p, const ApplyLaunch& a) {
+    plan_drop_graph(p);
+    if (std::getenv("SVDLUT_NO_GRAPH")) return SVDLUT_OK;   // plain launches instead
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+        return fail(SVDLUT_EDEVICE, "plan: stream create failed");
+    svdlut_status st = SVDLUT_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        st = fail(SVDLUT_EDEVICE, "plan: begin capture failed");
+    } else {
+        st = launch_apply(a, cs);
+        hipGraph_t g = nullptr;
+        const hipError_t e = hipStreamEndCapture(cs, &g);
+        if (st == SVDLUT_OK && e != hipSuccess) st = fail(SVDLUT_EDEVICE, "plan: end capture failed");
+        if (st == SVDLUT_OK) {
+            p->graph = g;
+            size_t n = 0;
+            if (hipGraphGetNodes(g, nullptr, &n) != hipSuccess || n != 1) {
+                st = fail(SVDLUT_EDEVICE, "plan: captured graph has unexpected shape");
+            } else {
+                (void)hipGraphGetNodes(g, &p->node, &n);
+                if (hipGraphInstantiate(&p->exec, g, nullptr, nullptr, 0) != hipSuccess)
+                    st = fail(SVDLUT_EDEVICE, "plan: graph instantiate failed");
+            }
+        } else if (g) {
+            (void)hipGraphDestroy(g);
+        }
+    }
+    (void)hipStreamDestroy(cs);
+    (void)hipGetLastError();
+    if (st == SVDLUT_OK) {
+        p->captured = a;
+        p->have_graph = true;
+    } else {
+        plan_drop_graph(p);
+    }
+    return st;
+}
+
+static bool same_buffers(const ApplyLaunch& a, const ApplyLaunch& b) {
+    return a.x == b.x && a.y == b.y && a.U == b.U && a.s == b.s && a.V == b.V && a.map == b.map &&
+           a.bias == b.bias && a.block == b.block && a.grid == b.grid;
+}
+
+static void plan_set_shape(svdlut_plan* p, int block, int bpc, const DeviceInfo& di) {
+    p->block = block;
+    const int64_t max_grid = static_cast<int64_t>(di.cus) * bpc;
+    const int64_t min_tiles = block / kWave;
+    p->grid = static_cast<int>(std::max<int64_t>(1, std::min(max_grid, (p->tiles + min_tiles - 1) / min_tiles)));
+}
+
+}  // namespace svdlut
+
+extern "C" {
+
+svdlut_status svdlut_plan_create(const svdlut_image_desc* descs, int32_t B, int32_t D, int32_t R,
+                                 svdlut_dtype io, svdlut_dtype map_dt, svdlut_plan** out) {
+    if (!descs || !out) return fail(SVDLUT_EINVAL, "plan_create: null pointer");
+    *out = nullptr;
+    if (B < 1) return fail(SVDLUT_EINVAL, "plan_create: B must be >= 1");
+    SVDLUT_TRY(check_lut_dims(D, R));
+    SVDLUT_TRY(check_dtype(io, "plan io"));
+    SVDLUT_TRY(check_dtype(map_dt, "plan map"));
+    auto p = new svdlut_plan();
+    p->B = B; p->D = D; p->R = R; p->io = io; p->map_dt = map_dt;
+    p->descs.resize(B);
+    p->tile_start.resize(B + 1);
+    int64_t t = 0;
+    for (int b = 0; b < B; ++b) {
+        const svdlut_image_desc& d = descs[b];
+        if (!dims_ok(d.H) || !dims_ok(d.W) || !dims_ok(d.h) || !dims_ok(d.w) || d.x_off < 0 || d.y_off < 0 ||
+            d.map_off < 0) {
+            delete p;
+            return fail(SVDLUT_EINVAL, "plan_create: descriptor " + std::to_string(b) + " out of range");
+        }
+        p->descs[b] = ImgGeom{d.H, d.W, d.h, d.w, d.x_off, d.y_off, d.map_off};
+        p->tile_start[b] = t;
+        t += static_cast<int64_t>(d.H) * ((d.W + kSeg - 1) / kSeg);
+        p->pixels += static_cast<int64_t>(d.H) * d.W;
+        p->ncol_max = std::max(p->ncol_max, map_cols_bound(d.W, d.w));
+        if (!map_fast_ok(d.W, d.w)) p->fast_map = 0;
+    }
+    p->tile_start[B] = t;
+    p->tiles = t;
+    const DeviceInfo& di = device_info();
+    p->device = di.device;
+    const std::string key = tune_key(p, di);
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        auto it = g_tune.find(key);
+        if (it != g_tune.end() && apply_lds_bytes(D, R, it->second.first, p->ncol_max) <= static_cast<size_t>(di.lds_per_block)) {
+            plan_set_shape(p, it->second.first, it->second.second, di);
+            p->tuned = 1;
+        }
+    }
+    if (!p->tuned) {
+        const int blk = default_block(D, R, p->ncol_max, di);
+        if (blk == 0) {
+            delete p;
+            return fail(SVDLUT_EUNSUPPORTED, "plan_create: map too wide for LDS staging");
+        }
+        plan_set_shape(p, blk, blocks_per_cu(D, R, blk, p->ncol_max, di), di);
+    }
+    if (hipMalloc(reinterpret_cast<void**>(&p->d_descs), sizeof(ImgGeom) * B) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&p->d_tiles), sizeof(int64_t) * (B + 1)) != hipSuccess) {
+        (void)hipGetLastError();
+        if (p->d_descs) (void)hipFree(p->d_descs);
+        delete p;
+        return fail(SVDLUT_ENOMEM, "plan_create: device table allocation failed");
+    }
+    if (hipMemcpy(p->d_descs, p->descs.data(), sizeof(ImgGeom) * B, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(p->d_tiles, p->tile_start.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipFree(p->d_descs);
+        (void)hipFree(p->d_tiles);
+        delete p;
+        return fail(SVDLUT_EDEVICE, "plan_create: descriptor upload failed");
+    }
+    *out = p;
+    return SVDLUT_OK;
+}
+
+static svdlut_status check_plan_ptrs(const svdlut_plan* p, const void* x, void* y, const float* U,
+                                     const float* s, const float* V, const void* map) {
+    if (!p) return fail(SVDLUT_EINVAL, "plan: null plan");
+    if (!x || !y || !U || !s || !V || !map) return fail(SVDLUT_EINVAL, "plan: null buffer pointer");
+    return SVDLUT_OK;
+}
+
+svdlut_status svdlut_plan_launch_direct(svdlut_plan* p, const void* x, void* y, const float* U,
+                                        const float* s, const float* V, const void* map, const float* bias,
+                                        hipStream_t stream) {
+    SVDLUT_TRY(check_plan_ptrs(p, x, y, U, s, V, map));
+    return launch_apply(plan_args(p, x, y, U, s, V, map, bias), stream);
+}
+
+svdlut_status svdlut_plan_launch(svdlut_plan* p, const void* x, void* y, const float* U, const float* s,
+                                 const float* V, const void* map, const float* bias, hipStream_t stream) {
+    SVDLUT_TRY(check_plan_ptrs(p, x, y, U, s, V, map));
+    const ApplyLaunch a = plan_args(p, x, y, U, s, V, map, bias);
+    if (!p->have_graph) {
+        const svdlut_status st = plan_capture(p, a);
+        if (st != SVDLUT_OK || !p->have_graph) return launch_apply(a, stream);   // plain launch fallback
+    } else if (!same_buffers(a, p->captured)) {
+        hipKernelNodeParams kp{};
+        if (hipGraphKernelNodeGetParams(p->node, &kp) != hipSuccess) {
+            (void)hipGetLastError();
+            SVDLUT_TRY(plan_capture(p, a));
+        } else {
+            ApplyLaunch arg = a;
+            void* args[1] = {&arg};
+            kp.kernelParams = args;
+            kp.extra = nullptr;
+            if (hipGraphExecKernelNodeSetParams(p->exec, p->node, &kp) != hipSuccess) {
+                (void)hipGetLastError();
+                SVDLUT_TRY(plan_capture(p, a));
+            } else {
+                p->captured = a;
+            }
+        }
+    }
+    if (!p->have_graph) return launch_apply(a, stream);
+    if (hipGraphLaunch(p->exec, stream) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SVDLUT_EDEVICE, "plan_launch: graph launch failed");
+    }
+    return SVDLUT_OK;
+}
+
+svdlut_status svdlut_plan_autotune(svdlut_plan* p, const void* x, void* y, const float* U, const float* s,
+                                   const float* V, const void* map, const float* bias, hipStream_t stream) {
+    SVDLUT_TRY(check_plan_ptrs(p, x, y, U, s, V, map));
+    const DeviceInfo& di = device_info();
+    struct Cand { int block, bpc; };
+    std::vector<Cand> cands;
+    for (int blk : {256, 512, 1024}) {
+        if (apply_lds_bytes(p->D, p->R, blk, p->ncol_max) > static_cast<size_t>(di.lds_per_block)) continue;
+        const int maxb = blocks_per_cu(p->D, p->R, blk, p->ncol_max, di);
+        for (int bpc = 1; bpc <= maxb; bpc *= 2) cands.push_back({blk, bpc});
+        if (maxb & (maxb - 1)) cands.push_back({blk, maxb});
+    }
+    if (cands.empty()) return fail(SVDLUT_EUNSUPPORTED, "plan_autotune: no candidate fits LDS");
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(SVDLUT_EDEVICE, "plan_autotune: event create failed");
+    float best = 1e30f;
+    Cand bestc = cands[0];
+    for (const Cand& c : cands) {
+        plan_set_shape(p, c.block, c.bpc, di);
+        const ApplyLaunch a = plan_args(p, x, y, U, s, V, map, bias);
+        svdlut_status st = launch_apply(a, stream);   // warm-up
+        if (st != SVDLUT_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
+        const int reps = 5;
+        (void)hipEventRecord(e0, stream);
+        for (int r = 0; r < reps; ++r) launch_apply(a, stream);
+        (void)hipEventRecord(e1, stream);
+        if (hipEventSynchronize(e1) != hipSuccess) {
+            (void)hipEventDestroy(e0); (void)hipEventDestroy(e1);
+            return fail(SVDLUT_EDEVICE, "plan_autotune: timing failed");
+        }
+        float ms = 0.f;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (ms < best) { best = ms; bestc = c; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    plan_set_shape(p, bestc.block, bestc.bpc, di);
+    p->tuned = 1;
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        tune_load_locked();
+        g_tune[tune_key(p, di)] = {bestc.block, bestc.bpc};
+        tune_save_locked();
+    }
+    plan_drop_graph(p);
+    return SVDLUT_OK;
+}
+
+svdlut_status svdlut_plan_get_info(const svdlut_plan* p, svdlut_plan_info* info) {
+    if (!p || !info) return fail(SVDLUT_EINVAL, "plan_get_info: null pointer");
+    info->pixels = p->pixels;
+    info->tiles = p->tiles;
+    info->block = p->block;
+    info->grid = p->grid;
+    info->tuned = p->tuned;
+    info->graph = p->have_graph ? 1 : 0;
+    return SVDLUT_OK;
+}
+
+svdlut_status svdlut_plan_destroy(svdlut_plan* p) {
+    if (!p) return SVDLUT_OK;
+    plan_drop_graph(p);
+    if (p->d_descs) (void)hipFree(p->d_descs);
+    if (p->d_tiles) (void)hipFree(p->d_tiles);
+    delete p;
+    return SVDLUT_OK;
+}
+
+}  // extern "C"

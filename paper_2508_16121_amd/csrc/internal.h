@@ -1,0 +1,94 @@
+// Internal declarations shared by the library's translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/svdlut.h"
+
+namespace svdlut {
+
+constexpr int kMaxD = 40;
+constexpr int kMaxR = 64;
+constexpr int kMaxDim = 65535;
+constexpr int kWave = 64;
+constexpr int kPxPerLane = 4;                      // pixels per lane per row segment
+constexpr int kSeg = kWave * kPxPerLane;           // pixels per row segment (one wave)
+constexpr int kMapStride = 12;                     // floats per staged map column (9 used, 16-B aligned)
+
+void set_error(const std::string& msg);
+svdlut_status fail(svdlut_status st, const std::string& msg);
+svdlut_status check_launch(const char* what);
+
+struct DeviceInfo {
+    int device = 0;
+    int cus = 256;
+    int lds_per_block = 65536;
+    int lds_per_cu = 163840;
+    std::string arch;
+};
+const DeviceInfo& device_info();
+
+// ---------------------------------------------------------------- LUT path geometry
+// Per-image geometry for the apply kernels.  Offsets are in elements.
+struct ImgGeom {
+    int32_t H, W, h, w;
+    int64_t x_off, y_off, map_off;
+};
+
+struct ApplyLaunch {
+    const void* x;
+    void* y;
+    const float* U;
+    const float* s;
+    const float* V;
+    const void* map;
+    const float* bias;
+    int32_t B, D, R;
+    // uniform batch (descs == nullptr): dims below; uneven batch: per-image descs on device
+    int32_t H, W, h, w;
+    const ImgGeom* descs;          // device, uneven batch only
+    const int64_t* tile_start;     // device [B+1] prefix of row segments, uneven batch only
+    int64_t total_tiles;
+    int32_t ncol_max;              // staged map columns per wave
+    int32_t fast_map;              // 1: map at most 1/3 of image resolution (piecewise path)
+    int32_t block;                 // threads per workgroup
+    int32_t grid;                  // workgroups
+    svdlut_dtype io, map_dt;
+};
+
+size_t apply_lds_bytes(int D, int R, int block, int ncol_max);
+int map_cols_bound(int W, int w);
+bool map_fast_ok(int W, int w);
+svdlut_status launch_apply(const ApplyLaunch& a, hipStream_t st);
+svdlut_status launch_reconstruct(const float* U, const float* s, const float* V, float* T,
+                                 int n, int D, int R, hipStream_t st);
+
+struct BwdLaunch {
+    const void* x;
+    const void* dy;
+    const float* U;
+    const float* s;
+    const float* V;
+    const void* map;
+    void* dx;
+    float* dU;
+    float* ds;
+    float* dV;
+    float* dmap;
+    float* dbias;
+    float* dT;                     // workspace [B][9][D][D]
+    int32_t B, H, W, h, w, D, R;
+    svdlut_dtype io, map_dt;
+};
+svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st);
+
+// ---------------------------------------------------------------- generator
+svdlut_status launch_loss(const void* y, const void* t, svdlut_dtype io, int64_t n, int kind,
+                          float* loss, void* dy, float* partial, int nblocks, hipStream_t st);
+int loss_blocks(int64_t n);
+
+}  // namespace svdlut

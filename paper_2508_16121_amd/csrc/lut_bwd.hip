@@ -1,0 +1,442 @@
+// Backward of the fused 2D-LUT transform: dL/dT (-> dU, ds, dV), dL/dmap, dL/dx, dL/dbias.
+//
+// Decomposition.  Each image gets `gpi` workgroups; workgroup j of image b processes a
+// contiguous band of row segments.  It rebuilds T into LDS, accumulates its share of dT
+// in a second LDS copy with LDS float atomics, and writes that copy to its own slot of a
+// partial buffer (plain stores).  A second kernel sums the gpi partials of each LUT in a
+// fixed order and applies the chain rule of T = U diag(s) V^T.  dmap contributions go
+// first to per-wave staged map columns, then to a workgroup copy of the map rows its
+// band touches (LDS atomics), then to global memory (one atomic per touched map element
+// per workgroup).  dx is written directly.
+#include "lut_common.h"
+
+#include <algorithm>
+
+namespace svdlut {
+
+namespace {
+
+constexpr int kBwdStride = 9;   // floats per staged map column in the backward
+
+struct BwdDev {
+    BwdLaunch a;
+    int gpi;            // workgroups per image
+    int64_t per;        // tiles per workgroup
+    int ncol_max;       // staged columns per wave
+    int mrows;          // map rows held per workgroup (0: flush dmap straight to global)
+    int fast_map;
+    int want_dT, want_dmap, want_dx, want_db;
+};
+
+__device__ __forceinline__ void lds_add(float* p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ void gbl_add(float* p, float v) {
+    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <typename IO, typename MT, bool FASTMAP, bool VEC>
+__device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, const float* Tl,
+                                         float* dTl, float* macc, int row_lo, float* stage,
+                                         float* dstage, float (&dbsum)[3]) {
+    const BwdLaunch& a = P.a;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int H = a.H, W = a.W, h = a.h, w = a.w, D = a.D;
+    const int nseg = (W + kSeg - 1) / kSeg;
+    const int y = static_cast<int>(lt / nseg);
+    const int seg = static_cast<int>(lt - static_cast<int64_t>(y) * nseg);
+    const int xs = seg * kSeg;
+    const int x0 = xs + lane * kPxPerLane;
+    const int xlast = min(xs + kSeg, W) - 1;
+
+    const AxisMap ay = make_axis(H, h);
+    int iv; uint32_t remv;
+    axis_left(ay, y, iv, remv);
+    const float dv = static_cast<float>(remv) * ay.inv;
+    const int iv1 = min(iv + 1, h - 1);
+    const AxisMap ax = make_axis(W, w);
+    int clo; uint32_t rlo;
+    axis_left(ax, xs, clo, rlo);
+    int chi; uint32_t rhi;
+    axis_left(ax, xlast, chi, rhi);
+    chi = min(chi + 2, w - 1);
+    const int ncols = chi - clo + 1;
+
+    const int64_t mplane = static_cast<int64_t>(h) * w;
+    const MT* mb = reinterpret_cast<const MT*>(a.map) + static_cast<int64_t>(b) * 9 * mplane;
+    for (int j = lane; j < ncols; j += kWave) {
+        const int col = clo + j;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            const float v0 = ldf<MT>(mb + l * mplane + static_cast<int64_t>(iv) * w + col);
+            const float v1 = ldf<MT>(mb + l * mplane + static_cast<int64_t>(iv1) * w + col);
+            stage[j * kBwdStride + l] = fmaf(dv, v1 - v0, v0);
+            dstage[j * kBwdStride + l] = 0.f;
+        }
+    }
+    wave_sync();
+
+    const int64_t plane = static_cast<int64_t>(H) * W;
+    const int64_t img = static_cast<int64_t>(b) * 3 * plane + static_cast<int64_t>(y) * W;
+    if (x0 < W) {
+        float px[3][4], gy[3][4], dx[3][4];
+        const IO* xin = reinterpret_cast<const IO*>(a.x) + img;
+        const IO* gin = reinterpret_cast<const IO*>(a.dy) + img;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            load_px4<IO, VEC>(xin + c * plane, x0, W, px[c]);
+            load_px4<IO, VEC>(gin + c * plane, x0, W, gy[c]);
+        }
+        int c0; uint32_t rem0;
+        axis_left(ax, x0, c0, rem0);
+        const float Dm1 = static_cast<float>(D - 1);
+        const int Dm2 = D - 2;
+        const int rowstep = lut_row_stride(D);
+
+        float r0[9], d01[9], d12[9], A0[9], A1[9], A2[9];
+        const int j0 = c0 - clo;
+        const int j1 = min(c0 + 1, w - 1) - clo;
+        const int j2 = min(c0 + 2, w - 1) - clo;
+        if (FASTMAP) {
+#pragma unroll
+            for (int l = 0; l < 9; ++l) {
+                const float v0 = stage[j0 * kBwdStride + l];
+                const float v1 = stage[j1 * kBwdStride + l];
+                const float v2 = stage[j2 * kBwdStride + l];
+                r0[l] = v0; d01[l] = v1 - v0; d12[l] = v2 - v1;
+                A0[l] = 0.f; A1[l] = 0.f; A2[l] = 0.f;
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dx[c][k] = 0.f;
+            if (x0 + k >= W) continue;
+            float S[9], ta = 0.f, tb = 0.f, du = 0.f;
+            int jk = 0, jk1 = 0;
+            if (FASTMAP) {
+                const uint32_t n = rem0 + static_cast<uint32_t>(k) * ax.num_step;
+                ta = static_cast<float>(min(n, ax.div.d)) * ax.inv;
+                tb = static_cast<float>(n > ax.div.d ? n - ax.div.d : 0u) * ax.inv;
+#pragma unroll
+                for (int l = 0; l < 9; ++l) S[l] = fmaf(tb, d12[l], fmaf(ta, d01[l], r0[l]));
+            } else {
+                int ck; uint32_t rk;
+                axis_left(ax, x0 + k, ck, rk);
+                du = static_cast<float>(rk) * ax.inv;
+                jk = ck - clo;
+                jk1 = min(ck + 1, w - 1) - clo;
+#pragma unroll
+                for (int l = 0; l < 9; ++l) {
+                    const float s0 = stage[jk * kBwdStride + l];
+                    S[l] = fmaf(du, stage[jk1 * kBwdStride + l] - s0, s0);
+                }
+            }
+            int ii[3]; float dd[3];
+#pragma unroll
+            for (int c = 0; c < 3; ++c) decode(px[c][k], Dm1, Dm2, ii[c], dd[c]);
+            float gx[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+            for (int c = 0; c < 3; ++c) dbsum[c] += gy[c][k];
+#pragma unroll
+            for (int p = 0; p < 3; ++p) {
+                const int al = (p == 2) ? 1 : 0;
+                const int be = (p == 0) ? 1 : 2;
+                const float da = dd[al], db = dd[be];
+                const float w11 = da * db;
+                const float w10 = da - w11;
+                const float w01 = db - w11;
+                const float w00 = 1.f - da - db + w11;
+                const int slot = lut_slot(p, ii[al], ii[be], 0, D);
+                const float* t0 = Tl + slot;
+                const float* t1 = t0 + rowstep;
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float T00 = t0[c], T01 = t0[3 + c], T10 = t1[c], T11 = t1[3 + c];
+                    const float g = gy[c][k] * S[3 * c + p];
+                    if (P.want_dT) {
+                        float* q0 = dTl + slot;
+                        float* q1 = q0 + rowstep;
+                        lds_add(q0 + c, g * w00);
+                        lds_add(q1 + c, g * w10);
+                        lds_add(q0 + 3 + c, g * w01);
+                        lds_add(q1 + 3 + c, g * w11);
+                    }
+                    gx[al] = fmaf(g, (1.f - db) * (T10 - T00) + db * (T11 - T01), gx[al]);
+                    gx[be] = fmaf(g, (1.f - da) * (T01 - T00) + da * (T11 - T10), gx[be]);
+                    if (P.want_dmap) {
+                        float phi = w00 * T00;
+                        phi = fmaf(w10, T10, phi);
+                        phi = fmaf(w01, T01, phi);
+                        phi = fmaf(w11, T11, phi);
+                        const float gp = gy[c][k] * phi;
+                        const int l = 3 * c + p;
+                        if (FASTMAP) {
+                            A0[l] = fmaf(gp, 1.f - ta, A0[l]);
+                            A1[l] = fmaf(gp, ta - tb, A1[l]);
+                            A2[l] = fmaf(gp, tb, A2[l]);
+                        } else {
+                            lds_add(dstage + jk * kBwdStride + l, gp * (1.f - du));
+                            lds_add(dstage + jk1 * kBwdStride + l, gp * du);
+                        }
+                    }
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float xv = px[c][k];
+                dx[c][k] = (xv >= 0.f && xv <= 1.f) ? Dm1 * gx[c] : 0.f;
+            }
+        }
+        if (FASTMAP && P.want_dmap) {
+#pragma unroll
+            for (int l = 0; l < 9; ++l) {
+                lds_add(dstage + j0 * kBwdStride + l, A0[l]);
+                lds_add(dstage + j1 * kBwdStride + l, A1[l]);
+                lds_add(dstage + j2 * kBwdStride + l, A2[l]);
+            }
+        }
+        if (P.want_dx) {
+            IO* dxo = reinterpret_cast<IO*>(a.dx) + img;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) store_px4<IO, VEC>(dxo + c * plane, x0, W, dx[c]);
+        }
+    }
+    wave_sync();
+    if (P.want_dmap) {
+        // distribute the staged column sums to the two map rows around y
+        for (int j = lane; j < ncols; j += kWave) {
+            const int col = clo + j;
+#pragma unroll
+            for (int l = 0; l < 9; ++l) {
+                const float v = dstage[j * kBwdStride + l];
+                const float v0 = v * (1.f - dv), v1 = v * dv;
+                if (P.mrows > 0) {
+                    lds_add(macc + (l * P.mrows + (iv - row_lo)) * w + col, v0);
+                    if (iv1 != iv) lds_add(macc + (l * P.mrows + (iv1 - row_lo)) * w + col, v1);
+                } else {
+                    float* dm = a.dmap + static_cast<int64_t>(b) * 9 * mplane + l * mplane;
+                    gbl_add(dm + static_cast<int64_t>(iv) * w + col, v0);
+                    if (iv1 != iv) gbl_add(dm + static_cast<int64_t>(iv1) * w + col, v1);
+                }
+            }
+        }
+        wave_sync();
+    }
+}
+
+template <typename IO, typename MT, bool FASTMAP>
+__global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
+    extern __shared__ float smem[];
+    const BwdLaunch& a = P.a;
+    const int D = a.D;
+    const int nlut = lut_floats(D);
+    float* Tl = smem;
+    float* dTl = Tl + nlut;
+    float* macc = dTl + nlut;
+    const int macc_n = P.mrows * 9 * a.w;
+    float* aux = macc + ((macc_n + 3) & ~3);
+    const int nw = blockDim.x / kWave;
+    const int wave = threadIdx.x / kWave;
+    float* stage = aux + wave * 2 * P.ncol_max * kBwdStride;
+    float* dstage = stage + P.ncol_max * kBwdStride;
+
+    const int lb = logical_block(blockIdx.x, gridDim.x);
+    const int b = lb / P.gpi;
+    const int j = lb - b * P.gpi;
+    const int nseg = (a.W + kSeg - 1) / kSeg;
+    const int64_t tpi = static_cast<int64_t>(a.H) * nseg;
+    const int64_t t0 = static_cast<int64_t>(j) * P.per;
+    const int64_t t1 = min(tpi, t0 + P.per);
+
+    // map rows this band touches
+    int row_lo = 0;
+    if (t0 < t1) {
+        const AxisMap ay = make_axis(a.H, a.h);
+        uint32_t r;
+        axis_left(ay, static_cast<int>(t0 / nseg), row_lo, r);
+    }
+    const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
+    stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R,
+               min(a.R, 8));
+    for (int e = threadIdx.x; e < nlut; e += blockDim.x) dTl[e] = 0.f;
+    for (int e = threadIdx.x; e < macc_n; e += blockDim.x) macc[e] = 0.f;
+    __syncthreads();
+
+    float dbsum[3] = {0.f, 0.f, 0.f};
+    const int64_t plane = static_cast<int64_t>(a.H) * a.W;
+    const bool base_ok = ((plane | a.W) & 3) == 0 &&
+                         ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.dy) |
+                           reinterpret_cast<uintptr_t>(a.dx)) & (4 * sizeof(IO) - 1)) == 0;
+    for (int64_t t = t0 + wave; t < t1; t += nw) {
+        const int xs = static_cast<int>(t % nseg) * kSeg;
+        if (base_ok && xs + kSeg <= a.W)
+            bwd_tile<IO, MT, FASTMAP, true>(P, b, t, Tl, dTl, macc, row_lo, stage, dstage, dbsum);
+        else
+            bwd_tile<IO, MT, FASTMAP, false>(P, b, t, Tl, dTl, macc, row_lo, stage, dstage, dbsum);
+    }
+    __syncthreads();
+
+    if (P.want_dT) {
+        float* part = a.dT + (static_cast<size_t>(b) * P.gpi + j) * nlut;
+        for (int e = threadIdx.x; e < nlut; e += blockDim.x) part[e] = dTl[e];
+    }
+    if (P.want_dmap && P.mrows > 0 && t0 < t1) {
+        const int64_t mplane = static_cast<int64_t>(a.h) * a.w;
+        for (int e = threadIdx.x; e < macc_n; e += blockDim.x) {
+            const int l = e / (P.mrows * a.w);
+            const int rr = (e / a.w) % P.mrows;
+            const int col = e % a.w;
+            const int row = row_lo + rr;
+            const float v = macc[e];
+            if (row < a.h && v != 0.f)
+                gbl_add(a.dmap + static_cast<int64_t>(b) * 9 * mplane + l * mplane +
+                            static_cast<int64_t>(row) * a.w + col, v);
+        }
+    }
+    if (P.want_db) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float v = dbsum[c];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if ((threadIdx.x & 63) == 0) gbl_add(a.dbias + 3 * b + c, v);
+        }
+    }
+}
+
+// Sum the per-workgroup dT partials (fixed order) and apply the chain rule of
+// T = U diag(s) V^T: dU = dT V diag(s), dV = dT^T U diag(s), ds_k = sum_i U_ik (dT V)_ik.
+__global__ void __launch_bounds__(256) factor_grad_kernel(const float* __restrict__ part, int gpi,
+                                                          const float* __restrict__ U,
+                                                          const float* __restrict__ s,
+                                                          const float* __restrict__ V,
+                                                          float* __restrict__ dU, float* __restrict__ ds,
+                                                          float* __restrict__ dV, int D, int R) {
+    extern __shared__ float sm[];
+    const int bl = blockIdx.x;          // b*9 + l
+    const int b = bl / 9, l = bl - 9 * (bl / 9);
+    const int c = l / 3, p = l - 3 * (l / 3);
+    const int nlut = lut_floats(D);
+    float* dT = sm;                     // [D][D]
+    float* Us = dT + D * D;             // [D][R]
+    float* Vs = Us + D * R;             // [D][R]
+    float* Pm = Vs + D * R;             // [D][R]  dT V
+    const float* u = U + static_cast<size_t>(bl) * D * R;
+    const float* v = V + static_cast<size_t>(bl) * D * R;
+    const float* sv = s + static_cast<size_t>(bl) * R;
+    for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
+        const int i = e / D, jj = e - (e / D) * D;
+        const float* src = part + static_cast<size_t>(b) * gpi * nlut + lut_slot(p, i, jj, c, D);
+        float acc = 0.f;
+        for (int g = 0; g < gpi; ++g) acc += src[static_cast<size_t>(g) * nlut];
+        dT[e] = acc;
+    }
+    for (int e = threadIdx.x; e < D * R; e += blockDim.x) { Us[e] = u[e]; Vs[e] = v[e]; }
+    __syncthreads();
+    for (int e = threadIdx.x; e < D * R; e += blockDim.x) {
+        const int i = e / R, k = e - (e / R) * R;
+        float accP = 0.f, accQ = 0.f;
+        for (int jj = 0; jj < D; ++jj) {
+            accP = fmaf(dT[i * D + jj], Vs[jj * R + k], accP);   // (dT V)_ik
+            accQ = fmaf(dT[jj * D + i], Us[jj * R + k], accQ);   // (dT^T U)_ik
+        }
+        Pm[e] = accP;
+        dU[static_cast<size_t>(bl) * D * R + e] = accP * sv[k];
+        dV[static_cast<size_t>(bl) * D * R + e] = accQ * sv[k];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < R; k += blockDim.x) {
+        float acc = 0.f;
+        for (int i = 0; i < D; ++i) acc = fmaf(Us[i * R + k], Pm[i * R + k], acc);
+        ds[static_cast<size_t>(bl) * R + k] = acc;
+    }
+}
+
+__global__ void zero_kernel(float* p, int64_t n) {
+    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
+         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
+        p[i] = 0.f;
+}
+
+}  // namespace
+
+constexpr int kBwdPartials = 512;
+
+int bwd_groups_per_image(int B) { return std::max(1, kBwdPartials / std::max(B, 1)); }
+
+size_t bwd_workspace_bytes(int B, int D) {
+    const size_t nlut = static_cast<size_t>(lut_floats(D));
+    return sizeof(float) * nlut * static_cast<size_t>(B) * bwd_groups_per_image(B);
+}
+
+static size_t bwd_lds(int D, int block, int ncol_max, int mrows, int w, int R) {
+    const size_t nlut = static_cast<size_t>(lut_floats(D));
+    const size_t macc = (static_cast<size_t>(mrows) * 9 * w + 3) & ~static_cast<size_t>(3);
+    const size_t stage = static_cast<size_t>(block / kWave) * 2 * ncol_max * kBwdStride;
+    const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
+    return sizeof(float) * (2 * nlut + macc + std::max(stage, scratch));
+}
+
+svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
+    const DeviceInfo& di = device_info();
+    BwdDev P;
+    P.a = a;
+    P.gpi = bwd_groups_per_image(a.B);
+    const int nseg = (a.W + kSeg - 1) / kSeg;
+    const int64_t tpi = static_cast<int64_t>(a.H) * nseg;
+    P.per = (tpi + P.gpi - 1) / P.gpi;
+    P.ncol_max = map_cols_bound(a.W, a.w);
+    P.fast_map = map_fast_ok(a.W, a.w) ? 1 : 0;
+    P.want_dT = a.dU != nullptr;
+    P.want_dmap = a.dmap != nullptr;
+    P.want_dx = a.dx != nullptr;
+    P.want_db = a.dbias != nullptr;
+    // map rows touched by one band of P.per segments
+    const int64_t band_rows = P.per / nseg + 2;
+    const int64_t mr = (a.H > 1) ? (band_rows * (a.h - 1)) / (a.H - 1) + 3 : 1;
+    int mrows = static_cast<int>(std::min<int64_t>(a.h, mr));
+    int block = 0;
+    const int blocks[2] = {512, 256};
+    for (int pass = 0; pass < 2 && block == 0; ++pass) {
+        for (int bk : blocks) {
+            if (bwd_lds(a.D, bk, P.ncol_max, mrows, a.w, a.R) <= static_cast<size_t>(di.lds_per_block)) {
+                block = bk;
+                break;
+            }
+        }
+        if (block == 0) mrows = 0;   // too many map columns: send dmap straight to global atomics
+    }
+    if (block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply_bwd: map too wide for the LDS staging");
+    P.mrows = P.want_dmap ? mrows : 0;
+    const size_t lds = bwd_lds(a.D, block, P.ncol_max, P.mrows, a.w, a.R);
+
+    if (a.dmap) hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, a.dmap,
+                                   static_cast<int64_t>(a.B) * 9 * a.h * a.w);
+    if (a.dbias) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, a.dbias,
+                                    static_cast<int64_t>(a.B) * 3);
+    const int grid = a.B * P.gpi;
+#define SVDLUT_BWD(IO, MT)                                                                      \
+    do {                                                                                        \
+        if (P.fast_map)                                                                         \
+            hipLaunchKernelGGL((apply_bwd_kernel<IO, MT, true>), dim3(grid), dim3(block), lds, st, P); \
+        else                                                                                    \
+            hipLaunchKernelGGL((apply_bwd_kernel<IO, MT, false>), dim3(grid), dim3(block), lds, st, P); \
+    } while (0)
+    if (a.io == SVDLUT_F32) {
+        if (a.map_dt == SVDLUT_F32) SVDLUT_BWD(float, float); else SVDLUT_BWD(float, __half);
+    } else {
+        if (a.map_dt == SVDLUT_F32) SVDLUT_BWD(__half, float); else SVDLUT_BWD(__half, __half);
+    }
+#undef SVDLUT_BWD
+    svdlut_status stt = check_launch("apply_bwd");
+    if (stt != SVDLUT_OK) return stt;
+    if (P.want_dT) {
+        const size_t lds2 = sizeof(float) * (static_cast<size_t>(a.D) * a.D + 3 * static_cast<size_t>(a.D) * a.R);
+        hipLaunchKernelGGL(factor_grad_kernel, dim3(a.B * 9), dim3(256), lds2, st, a.dT, P.gpi,
+                           a.U, a.s, a.V, a.dU, a.ds, a.dV, a.D, a.R);
+        stt = check_launch("factor_grad");
+    }
+    return stt;
+}
+
+}  // namespace svdlut

@@ -1,0 +1,340 @@
+// Forward kernels of the 2D-LUT path: standalone LUT reconstruction and the fused
+// reconstruct + spatially weighted 2D-LUT transform (persistent, one launch per batch).
+#include "lut_common.h"
+
+#include <algorithm>
+
+namespace svdlut {
+
+// ---------------------------------------------------------------- standalone reconstruction
+// One workgroup per LUT: T[i][j] = sum_k U[i][k] s[k] V[j][k].
+__global__ void __launch_bounds__(256) reconstruct_kernel(const float* __restrict__ U,
+                                                          const float* __restrict__ s,
+                                                          const float* __restrict__ V,
+                                                          float* __restrict__ T, int D, int R) {
+    extern __shared__ float sm[];
+    const int n = blockIdx.x;
+    float* Us = sm;            // [D][R]
+    float* Vs = sm + D * R;    // [D][R]
+    const float* u = U + static_cast<size_t>(n) * D * R;
+    const float* v = V + static_cast<size_t>(n) * D * R;
+    const float* sv = s + static_cast<size_t>(n) * R;
+    for (int e = threadIdx.x; e < D * R; e += blockDim.x) {
+        Us[e] = u[e] * sv[e % R];
+        Vs[e] = v[e];
+    }
+    __syncthreads();
+    float* t = T + static_cast<size_t>(n) * D * D;
+    for (int o = threadIdx.x; o < D * D; o += blockDim.x) {
+        const int i = o / D, j = o - (o / D) * D;
+        float acc = 0.f;
+        for (int k = 0; k < R; ++k) acc = fmaf(Us[i * R + k], Vs[j * R + k], acc);
+        t[o] = acc;
+    }
+}
+
+svdlut_status launch_reconstruct(const float* U, const float* s, const float* V, float* T,
+                                 int n, int D, int R, hipStream_t st) {
+    const size_t lds = 2 * sizeof(float) * D * R;
+    hipLaunchKernelGGL(reconstruct_kernel, dim3(n), dim3(256), lds, st, U, s, V, T, D, R);
+    return check_launch("reconstruct");
+}
+
+// ---------------------------------------------------------------- fused apply
+// Work unit ("tile"): one row segment of kSeg = 256 pixels of one image, processed by one
+// wave (4 consecutive pixels per lane).  Tiles are numbered image-major, row-major.  Each
+// workgroup takes a contiguous chunk of tiles; within each image the chunk is split into
+// contiguous per-wave runs.  Before the first tile of an image the workgroup rebuilds that
+// image's LUTs into LDS; each wave's first pixel loads are already in flight by then, and
+// every tile's loads are issued one tile ahead.
+//
+// Spatial map: per tile the wave stages, for every map column the segment touches, the
+// nine map channels blended between the two map rows around the tile's row
+// (r_l(col) = (1-dv) m_l[iv][col] + dv m_l[iv+1][col]).  When the map has at most a third
+// of the image's resolution (FASTMAP) a lane's 4 pixels lie within staged columns
+// c0..c0+2 and S_l = r0 + a*(r1-r0) + b*(r2-r1) with a = min(t, 1), b = max(t-1, 0),
+// t = u - c0; otherwise each pixel blends its own pair of columns.
+
+struct Geo {
+    int H, W, h, w;
+    int64_t x_off, y_off, map_off;
+    int64_t tile0;   // first tile of the image
+    int nseg;        // row segments per image row
+    bool vec_ok;     // image rows can use aligned 4-element accesses
+    AxisMap ax, ay;  // map coordinates along x (W -> w) and y (H -> h)
+};
+
+__device__ __forceinline__ Geo image_geo(const ApplyLaunch& a, int b, int io_bytes) {
+    Geo g;
+    if (a.descs) {
+        const ImgGeom d = a.descs[b];
+        g.H = d.H; g.W = d.W; g.h = d.h; g.w = d.w;
+        g.x_off = d.x_off; g.y_off = d.y_off; g.map_off = d.map_off;
+        g.tile0 = a.tile_start[b];
+    } else {
+        g.H = a.H; g.W = a.W; g.h = a.h; g.w = a.w;
+        const int64_t plane = static_cast<int64_t>(a.H) * a.W;
+        g.x_off = static_cast<int64_t>(b) * 3 * plane;
+        g.y_off = g.x_off;
+        g.map_off = static_cast<int64_t>(b) * 9 * a.h * a.w;
+        g.tile0 = static_cast<int64_t>(b) * a.H * ((a.W + kSeg - 1) / kSeg);
+    }
+    g.nseg = (g.W + kSeg - 1) / kSeg;
+    const int64_t plane = static_cast<int64_t>(g.H) * g.W;
+    g.vec_ok = ((g.x_off | g.y_off | plane | g.W) & 3) == 0 &&
+               ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.y)) &
+                (4 * static_cast<uintptr_t>(io_bytes) - 1)) == 0;
+    g.ax = make_axis(g.W, g.w);
+    g.ay = make_axis(g.H, g.h);
+    return g;
+}
+
+__device__ __forceinline__ int image_of_tile(const ApplyLaunch& a, int64_t t) {
+    if (!a.descs) {
+        const int64_t per = static_cast<int64_t>(a.H) * ((a.W + kSeg - 1) / kSeg);
+        return static_cast<int>(t / per);
+    }
+    int lo = 0, hi = a.B - 1;            // largest b with tile_start[b] <= t
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.tile_start[mid] <= t) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Pixels of the lane for the tile at row y, segment start xs: 3 channels x 4 pixels.
+template <typename IO>
+__device__ __forceinline__ void load_tile(const ApplyLaunch& a, const Geo& g, int y, int xs, float (&px)[3][4]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int x0 = min(xs + lane * kPxPerLane, g.W - 1);
+    const int64_t plane = static_cast<int64_t>(g.H) * g.W;
+    const IO* xin = reinterpret_cast<const IO*>(a.x) + g.x_off + static_cast<int64_t>(y) * g.W;
+    if (g.vec_ok && xs + kSeg <= g.W) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) load_px4<IO, true>(xin + c * plane, x0, g.W, px[c]);
+    } else {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) load_px4<IO, false>(xin + c * plane, x0, g.W, px[c]);
+    }
+}
+
+// Stage the tile's map columns (rows iv and iv+1 blended with weight dv) into the wave's
+// region; returns the first staged column.
+template <typename MT>
+__device__ __forceinline__ int stage_map(const ApplyLaunch& a, const Geo& g, int iv, float dv, int xs,
+                                         float* stage) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int xlast = min(xs + kSeg, g.W) - 1;
+    const int iv1 = min(iv + 1, g.h - 1);
+    int clo, chi; uint32_t r;
+    axis_left(g.ax, xs, clo, r);
+    axis_left(g.ax, xlast, chi, r);
+    chi = min(chi + 2, g.w - 1);
+    const int ncols = chi - clo + 1;
+    const MT* m0 = reinterpret_cast<const MT*>(a.map) + g.map_off + static_cast<int64_t>(iv) * g.w + clo;
+    const int64_t rowd = static_cast<int64_t>(iv1 - iv) * g.w;
+    const int64_t mplane = static_cast<int64_t>(g.h) * g.w;
+    for (int j = lane; j < ncols; j += kWave) {
+        float* dst = stage + j * kMapStride;
+        const MT* src = m0 + j;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            const float v0 = ldf<MT>(src + l * mplane);
+            const float v1 = ldf<MT>(src + l * mplane + rowd);
+            dst[l] = fmaf(dv, v1 - v0, v0);
+        }
+    }
+    return clo;
+}
+
+template <typename IO, bool FASTMAP, bool VEC>
+__device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g, const float* Tl,
+                                             const float* stage, int clo, int D, int y, int xs,
+                                             const float (&px)[3][4], const float (&bias3)[3]) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int x0 = xs + lane * kPxPerLane;
+    if (x0 >= g.W) return;
+    int c0; uint32_t rem0;
+    axis_left(g.ax, x0, c0, rem0);
+    const float Dm1 = static_cast<float>(D - 1);
+    const int Dm2 = D - 2;
+    const int RS = lut_row_stride(D);
+    const int PS = lut_pair_stride(D);
+    float out[3][4];
+    float r0[9], d01[9], d12[9];
+    if (FASTMAP) {
+        const float* s0 = stage + (c0 - clo) * kMapStride;
+        const float* s1 = stage + (min(c0 + 1, g.w - 1) - clo) * kMapStride;
+        const float* s2 = stage + (min(c0 + 2, g.w - 1) - clo) * kMapStride;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            const float a0 = s0[l], a1 = s1[l], a2 = s2[l];
+            r0[l] = a0; d01[l] = a1 - a0; d12[l] = a2 - a1;
+        }
+    }
+    const uint32_t den = g.ax.div.d;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float S[9];
+        if (FASTMAP) {
+            const uint32_t n = rem0 + static_cast<uint32_t>(k) * g.ax.num_step;
+            const float ta = static_cast<float>(min(n, den)) * g.ax.inv;
+            const float tb = static_cast<float>(n > den ? n - den : 0u) * g.ax.inv;
+#pragma unroll
+            for (int l = 0; l < 9; ++l) S[l] = fmaf(tb, d12[l], fmaf(ta, d01[l], r0[l]));
+        } else {
+            int ck; uint32_t rk;
+            axis_left(g.ax, min(x0 + k, g.W - 1), ck, rk);
+            const float du = static_cast<float>(rk) * g.ax.inv;
+            const float* s0 = stage + (ck - clo) * kMapStride;
+            const float* s1 = stage + (min(ck + 1, g.w - 1) - clo) * kMapStride;
+#pragma unroll
+            for (int l = 0; l < 9; ++l) S[l] = fmaf(du, s1[l] - s0[l], s0[l]);
+        }
+        int ir, ig, ib; float dr, dg, db;
+        decode(px[0][k], Dm1, Dm2, ir, dr);
+        decode(px[1][k], Dm1, Dm2, ig, dg);
+        decode(px[2][k], Dm1, Dm2, ib, db);
+        float acc[3] = {bias3[0], bias3[1], bias3[2]};
+#pragma unroll
+        for (int p = 0; p < 3; ++p) {
+            const int ia = (p == 2) ? ig : ir;
+            const float da = (p == 2) ? dg : dr;
+            const int ib2 = (p == 0) ? ig : ib;
+            const float db2 = (p == 0) ? dg : db;
+            // bilinear weights: w11 = a b, w10 = a (1-b), w01 = (1-a) b, w00 = (1-a)(1-b)
+            const float w11 = da * db2;
+            const float w10 = da - w11;
+            const float w01 = db2 - w11;
+            const float w00 = (1.f - da) - w01;
+            const float* t0 = Tl + (p * PS + __umul24(ia, RS) + __umul24(ib2, 3));
+            const float* t1 = t0 + RS;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float phi = w00 * t0[c];
+                phi = fmaf(w10, t1[c], phi);
+                phi = fmaf(w01, t0[3 + c], phi);
+                phi = fmaf(w11, t1[3 + c], phi);
+                acc[c] = fmaf(S[3 * c + p], phi, acc[c]);
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < 3; ++c) out[c][k] = acc[c];
+    }
+    const int64_t plane = static_cast<int64_t>(g.H) * g.W;
+    IO* yout = reinterpret_cast<IO*>(a.y) + g.y_off + static_cast<int64_t>(y) * g.W;
+    store_px4<IO, VEC>(yout, x0, g.W, out[0]);
+    store_px4<IO, VEC>(yout + plane, x0, g.W, out[1]);
+    store_px4<IO, VEC>(yout + 2 * plane, x0, g.W, out[2]);
+}
+
+// Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave contiguous runs.
+template <typename IO, typename MT, bool FASTMAP>
+__global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
+    extern __shared__ float smem[];
+    const int D = a.D;
+    float* Tl = smem;
+    float* aux = smem + lut_floats(D);
+    const int nw = blockDim.x / kWave;
+    const int wave = threadIdx.x / kWave;
+    float* stage = aux + wave * a.ncol_max * kMapStride;
+
+    const int G = gridDim.x;
+    const int lb = logical_block(blockIdx.x, G);
+    const int64_t per = (a.total_tiles + G - 1) / G;
+    int64_t t0 = static_cast<int64_t>(lb) * per;
+    const int64_t t1 = min(a.total_tiles, t0 + per);
+    const int kc = min(a.R, 8);
+    while (t0 < t1) {
+        const int b = image_of_tile(a, t0);
+        const Geo g = image_geo(a, b, sizeof(IO));
+        const int64_t img_end = g.tile0 + static_cast<int64_t>(g.H) * g.nseg;
+        const int64_t te = min(t1, img_end);
+        // this wave's contiguous run of local tiles [w0, w0 + cnt)
+        const int n = static_cast<int>(te - t0);
+        const int q = (n + nw - 1) / nw;
+        const int w0 = static_cast<int>(t0 - g.tile0) + min(n, wave * q);
+        const int cnt = min(n, (wave + 1) * q) - min(n, wave * q);
+        int y = w0 / g.nseg;
+        int seg = w0 - y * g.nseg;
+        float px[3][4];
+        if (cnt > 0) load_tile<IO>(a, g, y, seg * kSeg, px);     // in flight during the LUT rebuild
+        const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
+        stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R, kc);
+        float bias3[3] = {0.f, 0.f, 0.f};
+        if (a.bias) {
+            bias3[0] = a.bias[3 * b]; bias3[1] = a.bias[3 * b + 1]; bias3[2] = a.bias[3 * b + 2];
+        }
+        int iv = 0; uint32_t remv = 0;
+        axis_left(g.ay, y, iv, remv);
+        for (int k = 0; k < cnt; ++k) {
+            const int xs = seg * kSeg;
+            const float dv = static_cast<float>(remv) * g.ay.inv;
+            const int clo = stage_map<MT>(a, g, iv, dv, xs, stage);
+            // next tile of the run
+            int ny = y, nseg_i = seg + 1;
+            if (nseg_i == g.nseg) { nseg_i = 0; ++ny; }
+            float nx[3][4];
+            if (k + 1 < cnt) load_tile<IO>(a, g, ny, nseg_i * kSeg, nx);
+            wave_sync();
+            if (g.vec_ok && xs + kSeg <= g.W)
+                compute_tile<IO, FASTMAP, true>(a, g, Tl, stage, clo, D, y, xs, px, bias3);
+            else
+                compute_tile<IO, FASTMAP, false>(a, g, Tl, stage, clo, D, y, xs, px, bias3);
+            wave_sync();   // the stage region is rewritten for the next tile
+            if (k + 1 < cnt) {
+#pragma unroll
+                for (int c = 0; c < 3; ++c)
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk) px[c][kk] = nx[c][kk];
+                if (ny != y) axis_left(g.ay, ny, iv, remv);
+                y = ny;
+                seg = nseg_i;
+            }
+        }
+        t0 = te;
+        __syncthreads();   // every wave is done with Tl and aux before the next image
+    }
+}
+
+int map_cols_bound(int W, int w) {
+    // columns touched by one segment: c0(last) - c0(first) <= floor(255*(w-1)/(W-1)) + 1, plus 2
+    if (w <= 1) return 1;
+    const int64_t span = (W > 1) ? (static_cast<int64_t>(kSeg - 1) * (w - 1)) / (W - 1) : 0;
+    return static_cast<int>(std::min<int64_t>(w, span + 4));
+}
+
+bool map_fast_ok(int W, int w) {
+    // a lane's 4 pixels must lie within two map cells: 3*(w-1) <= W-1
+    return static_cast<int64_t>(3) * (w - 1) <= static_cast<int64_t>(W - 1);
+}
+
+size_t apply_lds_bytes(int D, int R, int block, int ncol_max) {
+    const size_t lut = static_cast<size_t>(lut_floats(D));
+    (void)R;
+    const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
+    const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * kMapStride;
+    return sizeof(float) * (lut + std::max(scratch, stage));
+}
+
+template <typename IO, typename MT>
+static void launch_typed(const ApplyLaunch& a, size_t lds, hipStream_t st) {
+    if (a.fast_map)
+        hipLaunchKernelGGL((apply_kernel<IO, MT, true>), dim3(a.grid), dim3(a.block), lds, st, a);
+    else
+        hipLaunchKernelGGL((apply_kernel<IO, MT, false>), dim3(a.grid), dim3(a.block), lds, st, a);
+}
+
+svdlut_status launch_apply(const ApplyLaunch& a, hipStream_t st) {
+    const size_t lds = apply_lds_bytes(a.D, a.R, a.block, a.ncol_max);
+    if (a.io == SVDLUT_F32) {
+        if (a.map_dt == SVDLUT_F32) launch_typed<float, float>(a, lds, st);
+        else launch_typed<float, __half>(a, lds, st);
+    } else {
+        if (a.map_dt == SVDLUT_F32) launch_typed<__half, float>(a, lds, st);
+        else launch_typed<__half, __half>(a, lds, st);
+    }
+    return check_launch("apply");
+}
+
+}  // namespace svdlut

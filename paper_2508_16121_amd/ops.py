@@ -1,0 +1,168 @@
+"""Torch-facing wrappers of the C ABI: argument checks and marshalling only.
+
+Every computation runs in libsvdlut.so on the caller's current HIP stream; tensors must
+be contiguous device tensors.  Shapes follow include/svdlut.h:
+    x, y      [B][3][H][W]  float32 or float16
+    U, V      [B][9][D][R]  float32;  s [B][9][R] float32
+    smap      [B][9][h][w]  float32 or float16
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import torch
+
+from . import _lib
+from ._lib import F16, F32, check
+
+_DT = {torch.float32: F32, torch.float16: F16}
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _need(t, name, dtypes=(torch.float32,), ndim=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor (the library has no CPU path)")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}, expected one of {dtypes}")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions, got {tuple(t.shape)}")
+
+
+def _factors(U, s, V, B):
+    _need(U, "U", ndim=4); _need(s, "s", ndim=3); _need(V, "V", ndim=4)
+    if U.shape[0] != B or U.shape[1] != 9 or V.shape != U.shape or s.shape != (B, 9, U.shape[3]):
+        raise ValueError(f"factor shapes U{tuple(U.shape)} s{tuple(s.shape)} V{tuple(V.shape)} do not match B={B}")
+    return U.shape[2], U.shape[3]
+
+
+def reconstruct(U, s, V, out=None):
+    """T = U diag(s) V^T for every LUT: U, V [..., D, R], s [..., R] -> T [..., D, D]."""
+    _need(U, "U"); _need(s, "s"); _need(V, "V")
+    D, R = U.shape[-2], U.shape[-1]
+    n = U.numel() // (D * R)
+    if V.shape != U.shape or s.numel() != n * R:
+        raise ValueError("reconstruct: U, V must match and s must be [..., R]")
+    if out is None:
+        out = torch.empty(*U.shape[:-1], D, device=U.device, dtype=torch.float32)
+    _need(out, "out")
+    lib = _lib.load()
+    check(lib.svdlut_reconstruct(_ptr(U), _ptr(s), _ptr(V), _ptr(out), n, D, R, _stream()), "svdlut_reconstruct")
+    return out
+
+
+def apply(x, U, s, V, smap, bias=None, out=None):
+    """Fused reconstruct + spatially weighted 2D-LUT transform of a batch (svdlut_apply)."""
+    _need(x, "x", (torch.float32, torch.float16), 4)
+    B, C3, H, W = x.shape
+    if C3 != 3:
+        raise ValueError("x must be [B][3][H][W]")
+    D, R = _factors(U, s, V, B)
+    _need(smap, "smap", (torch.float32, torch.float16), 4)
+    if smap.shape[0] != B or smap.shape[1] != 9:
+        raise ValueError("smap must be [B][9][h][w]")
+    h, w = smap.shape[2], smap.shape[3]
+    if bias is not None:
+        _need(bias, "bias")
+        if bias.shape != (B, 3):
+            raise ValueError("bias must be [B][3]")
+    if out is None:
+        out = torch.empty_like(x)
+    _need(out, "out", (x.dtype,), 4)
+    lib = _lib.load()
+    check(lib.svdlut_apply(_ptr(x), _ptr(out), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap),
+                           _DT[smap.dtype], _ptr(bias), B, H, W, h, w, D, R, _stream()), "svdlut_apply")
+    return out
+
+
+def bwd_workspace(B, D, device):
+    n = _lib.load().svdlut_apply_bwd_workspace_size(B, D)
+    return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)
+
+
+def apply_bwd(x, dy, U, s, V, smap, need_dx=True, need_factors=True, need_map=True, need_bias=False,
+              ws=None):
+    """Gradients through svdlut_apply (svdlut_apply_bwd); returns a dict of the requested ones."""
+    _need(x, "x", (torch.float32, torch.float16), 4)
+    _need(dy, "dy", (x.dtype,), 4)
+    if dy.shape != x.shape:
+        raise ValueError("dy must have the shape of x")
+    B, _, H, W = x.shape
+    D, R = _factors(U, s, V, B)
+    _need(smap, "smap", (torch.float32, torch.float16), 4)
+    h, w = smap.shape[2], smap.shape[3]
+    dev = x.device
+    out = {}
+    dx = torch.empty_like(x) if need_dx else None
+    dU = torch.empty_like(U) if need_factors else None
+    ds = torch.empty_like(s) if need_factors else None
+    dV = torch.empty_like(V) if need_factors else None
+    dmap = torch.empty(B, 9, h, w, device=dev, dtype=torch.float32) if need_map else None
+    db = torch.empty(B, 3, device=dev, dtype=torch.float32) if need_bias else None
+    if need_factors and ws is None:
+        ws = bwd_workspace(B, D, dev)
+    lib = _lib.load()
+    wsb = ws.numel() * ws.element_size() if ws is not None else 0
+    check(lib.svdlut_apply_bwd(_ptr(x), _ptr(dy), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap),
+                               _DT[smap.dtype], _ptr(dx), _ptr(dU), _ptr(ds), _ptr(dV), _ptr(dmap), _ptr(db),
+                               B, H, W, h, w, D, R, _ptr(ws), wsb, _stream()), "svdlut_apply_bwd")
+    for k, v in (("dx", dx), ("dU", dU), ("ds", ds), ("dV", dV), ("dmap", dmap), ("db", db)):
+        if v is not None:
+            out[k] = v
+    return out
+
+
+class _ApplyFn(torch.autograd.Function):
+    """svdlut_apply forward with svdlut_apply_bwd as its backward."""
+
+    @staticmethod
+    def forward(ctx, x, U, s, V, smap, bias):
+        ctx.save_for_backward(x, U, s, V, smap)
+        ctx.has_bias = bias is not None
+        return apply(x, U, s, V, smap, bias)
+
+    @staticmethod
+    def backward(ctx, gy):
+        x, U, s, V, smap = ctx.saved_tensors
+        need = ctx.needs_input_grad
+        r = apply_bwd(x, gy.contiguous(), U, s, V, smap, need_dx=need[0],
+                      need_factors=need[1] or need[2] or need[3], need_map=need[4],
+                      need_bias=ctx.has_bias and need[5])
+        dmap = r.get("dmap")
+        if dmap is not None and dmap.dtype != smap.dtype:
+            dmap = dmap.to(smap.dtype)
+        return (r.get("dx"), r.get("dU") if need[1] else None, r.get("ds") if need[2] else None,
+                r.get("dV") if need[3] else None, dmap, r.get("db"))
+
+
+def apply_autograd(x, U, s, V, smap, bias=None):
+    """Differentiable svdlut_apply: gradients flow to x, U, s, V, smap (and bias)."""
+    return _ApplyFn.apply(x, U, s, V, smap, bias)
+
+
+def loss(y, target, kind="l1", want_grad=True):
+    """Mean L1 or MSE of y against target (svdlut_loss): returns (loss [1] float32, dL/dy or None)."""
+    _need(y, "y", (torch.float32, torch.float16))
+    _need(target, "target", (y.dtype,))
+    if target.shape != y.shape:
+        raise ValueError("target must have the shape of y")
+    k = {"l1": _lib.LOSS_L1, "mse": _lib.LOSS_MSE}[kind]
+    lib = _lib.load()
+    n = y.numel()
+    wsn = lib.svdlut_loss_workspace_size(n)
+    ws = torch.empty(wsn // 4 + 64, dtype=torch.float32, device=y.device)
+    out = torch.empty(1, dtype=torch.float32, device=y.device)
+    dy = torch.empty_like(y) if want_grad else None
+    check(lib.svdlut_loss(_ptr(y), _ptr(target), _DT[y.dtype], n, k, _ptr(out), _ptr(dy), _ptr(ws),
+                          ws.numel() * 4, _stream()), "svdlut_loss")
+    return out, dy

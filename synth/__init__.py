@@ -38,18 +38,17 @@ def image(g: np.random.Generator, H: int, W: int) -> np.ndarray:
     ph = g.uniform(0.0, 2.0 * math.pi, size=(3, N_SINES))
     xs = np.arange(W, dtype=np.float64) / W
     ys = np.arange(H, dtype=np.float64) / H
-    out = np.empty((3, H, W), dtype=np.float64)
+    out = np.empty((3, H, W), dtype=np.float32)
     for c in range(3):
-        acc = np.full((H, W), 0.5)
-        for k in range(N_SINES):
-            # sin(A + B) = sin A cos B + cos A sin B, built from two outer products
-            A = 2.0 * math.pi * fx[c, k] * xs + ph[c, k]
-            B = 2.0 * math.pi * fy[c, k] * ys
-            acc += a[c, k] * (np.outer(np.cos(B), np.sin(A)) + np.outer(np.sin(B), np.cos(A)))
-        out[c] = acc
-    out += g.normal(0.0, 0.02, size=out.shape)
+        # sum_k a_k sin(A_k(x) + B_k(y)) = [cos B | sin B] @ [a sin A ; a cos A]
+        A = 2.0 * math.pi * fx[c][:, None] * xs[None, :] + ph[c][:, None]      # [8][W]
+        B = 2.0 * math.pi * fy[c][:, None] * ys[None, :]                       # [8][H]
+        left = np.concatenate([np.cos(B), np.sin(B)], axis=0).T                # [H][16]
+        right = np.concatenate([a[c][:, None] * np.sin(A), a[c][:, None] * np.cos(A)], axis=0)
+        out[c] = (0.5 + left @ right).astype(np.float32)
+    out += np.float32(0.02) * g.standard_normal(size=out.shape, dtype=np.float32)
     np.clip(out, 0.0, 1.0, out=out)
-    return out.astype(np.float32)
+    return out
 
 
 def factors(g: np.random.Generator, n_img: int, D: int, R: int):
@@ -185,3 +184,34 @@ def pair_draws(idx: int, H: int = 256, W: int = 256, D: int = 33):
     base = image(g, H, W)
     lut3d, gain = degradation(g, D)
     return base, lut3d, gain
+
+
+def uneven_batch(n: int = 64, seed0: int = 3000, D: int = 33, R: int = 8, workers: int = 8, bases=BASE_SIZES):
+    """All images of the uneven batch (list of (x, U, s, V, map)), drawn on a thread pool."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(max(1, workers)) as ex:
+        return list(ex.map(lambda i: uneven_image(i, seed0, D, R, bases), range(n)))
+
+
+def pack_uneven(images, align: int = 64):
+    """Pack per-image arrays [(x [3][H][W], U, s, V, map [9][h][w]), ...] into flat planar
+    buffers.  Each image starts on an `align`-element boundary.  Returns
+    (x_flat float32, map_flat float32, U [B][9][D][R], s [B][9][R], V [B][9][D][R], descs)
+    where descs[b] = dict(H, W, h, w, x_off, y_off, map_off) in elements."""
+    descs, xo, mo = [], 0, 0
+    for x, U, s, V, m in images:
+        _, H, W = x.shape
+        _, h, w = m.shape
+        descs.append(dict(H=H, W=W, h=h, w=w, x_off=xo, y_off=xo, map_off=mo))
+        xo += -(-x.size // align) * align
+        mo += -(-m.size // align) * align
+    xf = np.zeros(xo, np.float32)
+    mf = np.zeros(mo, np.float32)
+    for d, (x, U, s, V, m) in zip(descs, images):
+        xf[d["x_off"]:d["x_off"] + x.size] = x.ravel()
+        mf[d["map_off"]:d["map_off"] + m.size] = m.ravel()
+    U = np.stack([im[1] for im in images])
+    s = np.stack([im[2] for im in images])
+    V = np.stack([im[3] for im in images])
+    return xf, mf, U, s, V, descs

@@ -1,0 +1,102 @@
+"""The C-ABI library without a GPU: it loads, exports every entry point include/svdlut.h declares,
+and rejects bad arguments with a status and a message before making any HIP call."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "svdlut.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2508_16121_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_2508_16121_amd import build
+        build.build(verbose=False)
+    return _lib.load()
+
+
+def header_symbols():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(svdlut_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_hot_path_calls():
+    syms = header_symbols()
+    for name in ("svdlut_reconstruct", "svdlut_apply", "svdlut_apply_bwd", "svdlut_generator_fwd",
+                 "svdlut_generator_bwd"):
+        assert name in syms
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [s for s in header_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_binding_signatures_cover_the_header():
+    from paper_2508_16121_amd import _lib
+    assert set(header_symbols()) == set(_lib.SIGS)
+
+
+def _err(lib):
+    return lib.svdlut_last_error().decode()
+
+
+def test_validation_happens_before_any_hip_call(lib):
+    null = None
+    fake = C.c_void_p(0x1000)        # never dereferenced: every call below fails validation first
+    # null pointers
+    assert lib.svdlut_reconstruct(null, fake, fake, fake, 9, 33, 8, null) == 1
+    assert "null" in _err(lib)
+    # D and R out of range
+    assert lib.svdlut_reconstruct(fake, fake, fake, fake, 9, 41, 8, null) == 1
+    assert lib.svdlut_reconstruct(fake, fake, fake, fake, 9, 33, 65, null) == 1
+    assert lib.svdlut_reconstruct(fake, fake, fake, fake, 0, 33, 8, null) == 1
+    args = [fake, fake, 0, fake, fake, fake, fake, 0, null]
+    # B, H, W, h, w, D, R
+    assert lib.svdlut_apply(*args, 0, 4, 4, 1, 1, 33, 8, null) == 1
+    assert lib.svdlut_apply(*args, 1, 0, 4, 1, 1, 33, 8, null) == 1
+    assert lib.svdlut_apply(*args, 1, 4, 70000, 1, 1, 33, 8, null) == 1
+    assert lib.svdlut_apply(*args, 1, 4, 4, 0, 1, 33, 8, null) == 1
+    assert lib.svdlut_apply(*args, 1, 4, 4, 1, 1, 1, 8, null) == 1
+    # unsupported dtype
+    bad = [fake, fake, 7, fake, fake, fake, fake, 0, null]
+    assert lib.svdlut_apply(*bad, 1, 4, 4, 1, 1, 33, 8, null) == 2
+    assert "dtype" in _err(lib)
+    # backward: partial factor trio, missing or short workspace
+    b = [fake, fake, 0, fake, fake, fake, fake, 0]
+    assert lib.svdlut_apply_bwd(*b, fake, fake, null, fake, null, null, 1, 8, 8, 1, 1, 33, 8, fake, 1 << 30, null) == 1
+    assert "all set" in _err(lib)
+    assert lib.svdlut_apply_bwd(*b, null, fake, fake, fake, null, null, 1, 8, 8, 1, 1, 33, 8, null, 0, null) == 1
+    assert lib.svdlut_apply_bwd(*b, null, fake, fake, fake, null, null, 1, 8, 8, 1, 1, 33, 8, fake, 16, null) == 1
+    assert "workspace" in _err(lib)
+    # nothing requested: a no-op success
+    assert lib.svdlut_apply_bwd(*b, null, null, null, null, null, null, 1, 8, 8, 1, 1, 33, 8, null, 0, null) == 0
+    # loss / adam
+    assert lib.svdlut_loss(fake, fake, 0, 0, 0, fake, null, fake, 64, null) == 1
+    assert lib.svdlut_loss(fake, fake, 0, 100, 5, fake, null, fake, 64, null) == 1
+    assert lib.svdlut_adam_step(fake, fake, fake, fake, 10, 1e-4, 0.9, 0.999, 1e-8, 0, null) == 1
+    assert lib.svdlut_adam_step(fake, fake, fake, fake, 10, 1e-4, 1.5, 0.999, 1e-8, 1, null) == 1
+    # plan
+    out = C.c_void_p()
+    assert lib.svdlut_plan_create(null, 1, 33, 8, 1, 1, C.byref(out)) == 1
+    assert lib.svdlut_plan_launch(null, fake, fake, fake, fake, fake, fake, null, null) == 1
+    assert lib.svdlut_plan_destroy(null) == 0
+    # generator
+    assert lib.svdlut_generator_fwd(null, fake, 0, 1, 256, 256, 33, 8, fake, fake, fake, fake, fake, 1 << 30, null) == 1
+    assert lib.svdlut_generator_fwd(fake, fake, 0, 1, 256, 256, 33, 8, fake, fake, fake, fake, fake, 16, null) == 1
+    assert lib.svdlut_generator_bwd(fake, null, fake, fake, fake, fake, 1, 33, 8, fake, 1 << 30, null) == 1
+
+
+def test_size_queries(lib):
+    assert lib.svdlut_generator_param_count(33, 8) == 872513
+    assert lib.svdlut_generator_param_count(17, 4) == 250217 + 9 * 140 * 129
+    assert lib.svdlut_generator_workspace_size(8, 33, 8) > 0
+    assert lib.svdlut_apply_bwd_workspace_size(16, 33) > 0
+    assert lib.svdlut_apply_bwd_workspace_size(0, 33) == 0
+    assert lib.svdlut_loss_workspace_size(1000) >= 4
+    assert lib.svdlut_version().startswith(b"svdlut")

@@ -1,0 +1,242 @@
+"""GPU parity of the backward 2D-LUT apply (dU, ds, dV, dmap, dx, dbias), the loss kernel and
+the autograd wrapper, against the fp64 oracle and central finite differences."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import lut as ol
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def svd():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2508_16121_amd as m
+    return m
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t.to(dtype) if dtype is not None else t
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def close(got, ref, rel=1e-4, what=""):
+    """Sums of many float32 atomic contributions: max-abs error within rel of the largest entry."""
+    scale = max(np.abs(ref).max(), 1e-30)
+    err = np.abs(got - ref).max()
+    assert err <= rel * scale, f"{what}: max-abs {err:.3e} vs scale {scale:.3e}"
+
+
+@pytest.mark.parametrize("shape", [
+    (2, 40, 70, 5, 3, 6, 9),       # small LUT, per-pixel map path
+    (1, 33, 300, 33, 8, 5, 38),    # two segments, ragged
+    (3, 64, 64, 17, 4, 8, 8),      # batch of three
+    (1, 1, 1, 9, 2, 1, 1),         # single pixel
+    (1, 16, 515, 33, 8, 1, 65),    # one map row
+])
+def test_backward_parity_small(svd, shape):
+    B, H, W, D, R, h, w = shape
+    say(f"bwd {shape}")
+    g = np.random.default_rng(sum(shape) + 7)
+    x = g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)
+    U, s, V = synth.factors(g, B, D, R)
+    m = synth.spatial_map(g, B, h, w)
+    G = g.normal(0, 1, (B, 3, H, W)).astype(np.float32)
+    r = svd.apply_bwd(dev(x), dev(G), dev(U), dev(s), dev(V), dev(m), need_bias=True)
+    ref = ol.apply_bwd(x, U, s, V, m, G)
+    for k in ("dU", "ds", "dV", "dmap", "db"):
+        close(host(r[k]), ref[k], 1e-4, k)
+    dx = host(r["dx"])
+    assert np.abs(dx - ref["dx"]).max() <= 1e-4 * max(np.abs(ref["dx"]).max(), 1e-30)
+    outside = (x < 0) | (x > 1)
+    assert np.all(dx[outside] == 0.0)
+
+
+def test_backward_subsets_and_overwrite(svd):
+    """Only the requested gradients are produced, and a second call overwrites (no accumulation)."""
+    c = synth.single(31, 48, 96, 9, 3, 6, 12)
+    G = np.random.default_rng(1).normal(size=c.x.shape).astype(np.float32)
+    args = [dev(a) for a in (c.x, G, c.U, c.s, c.V, c.smap)]
+    r1 = svd.apply_bwd(*args, need_dx=False, need_factors=True, need_map=False)
+    assert set(r1) == {"dU", "ds", "dV"}
+    r2 = svd.apply_bwd(*args, need_dx=False, need_factors=True, need_map=False)
+    assert np.array_equal(host(r1["ds"]), host(r2["ds"]))
+    r3 = svd.apply_bwd(*args, need_dx=True, need_factors=False, need_map=True)
+    assert set(r3) == {"dx", "dmap"}
+    ref = ol.apply_bwd(c.x, c.U, c.s, c.V, c.smap, G)
+    close(host(r3["dmap"]), ref["dmap"], 1e-4, "dmap")
+    close(host(r1["dU"]), ref["dU"], 1e-4, "dU")
+
+
+def test_loss_kernels(svd):
+    g = np.random.default_rng(2)
+    y = g.normal(size=(2, 3, 37, 41)).astype(np.float32)
+    t = g.normal(size=y.shape).astype(np.float32)
+    t[0, 0, 0, :5] = y[0, 0, 0, :5]
+    for kind, fn in (("l1", ol.l1_loss), ("mse", ol.mse_loss)):
+        v, dy = svd.loss(dev(y), dev(t), kind)
+        rv, rdy = fn(y, t)
+        assert abs(host(v)[0] - rv) <= 1e-5 * max(1.0, abs(rv))
+        assert np.abs(host(dy) - rdy).max() <= 1e-6 * np.abs(rdy).max()
+
+
+def test_autograd_matches_apply_bwd(svd):
+    c = synth.single(41, 40, 72, 17, 4, 5, 9)
+    x, U, s, V, m = (dev(a).requires_grad_() for a in (c.x, c.U, c.s, c.V, c.smap))
+    y = svd.apply_autograd(x, U, s, V, m)
+    G = torch.randn_like(y)
+    (y * G).sum().backward()
+    ref = ol.apply_bwd(c.x, c.U, c.s, c.V, c.smap, host(G))
+    close(host(U.grad), ref["dU"], 1e-4, "dU")
+    close(host(s.grad), ref["ds"], 1e-4, "ds")
+    close(host(V.grad), ref["dV"], 1e-4, "dV")
+    close(host(m.grad), ref["dmap"], 1e-4, "dmap")
+    close(host(x.grad), ref["dx"], 1e-4, "dx")
+
+
+# ------------------------------------------------------------------ full-size differentiation batch
+@pytest.fixture(scope="module")
+def c4(svd):
+    """16 x 3 x 512 x 512 fp32, D=33 R=8, 64x64 map, L1 against a seeded target: GPU forward,
+    loss and backward in the launch configuration the benchmark times."""
+    say("c4: generating inputs")
+    c = synth.diff_batch()
+    d = {k: dev(getattr(c, k)) for k in ("x", "U", "s", "V", "smap", "target")}
+    y = svd.apply(d["x"], d["U"], d["s"], d["V"], d["smap"])
+    loss, dy = svd.loss(y, d["target"], "l1")
+    r = svd.apply_bwd(d["x"], dy, d["U"], d["s"], d["V"], d["smap"])
+    out = {k: host(v) for k, v in r.items()}
+    out["y"] = host(y)
+    out["loss"] = float(host(loss)[0])
+    return c, out
+
+
+def _oracle_grad_one(c, b, N):
+    T = ol.reconstruct(c.U[b], c.s[b], c.V[b])
+    Y = ol.transform(c.x[b], T, c.smap[b])
+    G = np.sign(Y - c.target[b]) / N
+    r = ol.transform_bwd(c.x[b], T, c.smap[b], G)
+    dU, ds, dV = ol.factor_grads(r["dT"], c.U[b], c.s[b], c.V[b])
+    return Y, dict(dU=dU, ds=ds, dV=dV, dmap=r["dmap"], dx=r["dx"])
+
+
+def test_c4_forward_and_loss(c4):
+    c, out = c4
+    N = c.x.size
+    g = np.random.default_rng(44)
+    tot = 0.0
+    for b in range(c.x.shape[0]):
+        T = ol.reconstruct(c.U[b], c.s[b], c.V[b])
+        ys = g.integers(0, 512, 500); xs = g.integers(0, 512, 500)
+        ref = ol.transform_at(c.x[b], T, c.smap[b], ys, xs)
+        assert np.abs(out["y"][b][:, ys, xs] - ref).max() <= 1e-5
+    Y0 = ol.apply(c.x[:2], c.U[:2], c.s[:2], c.V[:2], c.smap[:2])
+    assert np.abs(out["y"][:2] - Y0).max() <= 1e-5
+    tot = np.abs(out["y"].astype(np.float64) - c.target).sum() / N
+    assert abs(out["loss"] - tot) <= 1e-5 * tot
+
+
+@pytest.mark.parametrize("b", [0, 15])
+def test_c4_gradients_match_oracle(c4, b):
+    c, out = c4
+    say(f"c4 oracle gradients, image {b}")
+    _, ref = _oracle_grad_one(c, b, c.x.size)
+    for k in ("dU", "ds", "dV", "dmap", "dx"):
+        close(out[k][b], ref[k], 1e-4, k)
+
+
+def test_c4_finite_differences(c4):
+    """Central differences (h = 1e-3) of the fp64 oracle's forward + L1 loss on image 0:
+    40 coordinates each of U, V, map and x and 20 of s (seed 4).  x coordinates lie more
+    than 2h(D-1) from a LUT knot and more than 2h from 0 and 1.  Only the pixels a
+    coordinate influences are re-evaluated (the others cancel exactly in the difference).
+    Tolerance |g - g_fd| <= 1e-3 max|g_fd| + 1e-2 |g_fd| per kind."""
+    c, out = c4
+    b, h = 0, 1e-3
+    N = c.x.size
+    x, U, s, V, m, tgt = c.x[b], c.U[b], c.s[b], c.V[b], c.smap[b], c.target[b]
+    D = U.shape[1]
+    H, W = x.shape[1:]
+    hm, wm = m.shape[1:]
+    g = np.random.default_rng(4)
+    dec = [ol.decode(x[a], D)[0] for a in range(3)]
+    allys, allxs = np.meshgrid(np.arange(H), np.arange(W), indexing="ij")
+
+    def loss_at(T, mm, xx, ys, xs):
+        Y = ol.transform_at(xx, T, mm, ys, xs)
+        return np.abs(Y - tgt[:, ys, xs]).sum() / N
+
+    def fd_factor(kind, l, i, k):
+        cp = {"U": U.copy(), "s": s.copy(), "V": V.copy()}
+        if kind == "U":
+            a = ol.PAIRS[l % 3][0]; sel = (dec[a] == i) | (dec[a] == i - 1)
+        elif kind == "V":
+            bb = ol.PAIRS[l % 3][1]; sel = (dec[bb] == i) | (dec[bb] == i - 1)
+        else:
+            sel = np.ones((H, W), bool)
+        ys, xs = allys[sel], allxs[sel]
+        vals = []
+        for sgn in (1, -1):
+            q = {k2: v.copy() for k2, v in cp.items()}
+            if kind == "s":
+                q["s"][l, k] += sgn * h
+            else:
+                q[kind][l, i, k] += sgn * h
+            vals.append(loss_at(ol.reconstruct(q["U"], q["s"], q["V"]), m, x, ys, xs))
+        return (vals[0] - vals[1]) / (2 * h)
+
+    T = ol.reconstruct(U, s, V)
+    res = {}
+    for kind, n in (("U", 40), ("V", 40), ("s", 20)):
+        pairs = []
+        for _ in range(n):
+            l, i, k = int(g.integers(0, 9)), int(g.integers(0, D)), int(g.integers(0, U.shape[2]))
+            gpu = out["d" + kind][b][l, k] if kind == "s" else out["d" + kind][b][l, i, k]
+            pairs.append((gpu, fd_factor(kind, l, i, k)))
+        res[kind] = pairs
+    # map coordinates: pixels within one map cell of the vertex
+    pairs = []
+    iv_all, _ = ol.axis_coords(H, hm)
+    iu_all, _ = ol.axis_coords(W, wm)
+    for _ in range(40):
+        l, r, cc = int(g.integers(0, 9)), int(g.integers(0, hm)), int(g.integers(0, wm))
+        rows = np.nonzero((iv_all == r) | (iv_all == r - 1) | (np.minimum(iv_all + 1, hm - 1) == r))[0]
+        cols = np.nonzero((iu_all == cc) | (iu_all == cc - 1) | (np.minimum(iu_all + 1, wm - 1) == cc))[0]
+        ys, xs = np.meshgrid(rows, cols, indexing="ij")
+        ys, xs = ys.ravel(), xs.ravel()
+        vals = []
+        for sgn in (1, -1):
+            mm = m.astype(np.float64).copy(); mm[l, r, cc] += sgn * h
+            vals.append(loss_at(T, mm, x, ys, xs))
+        pairs.append((out["dmap"][b][l, r, cc], (vals[0] - vals[1]) / (2 * h)))
+    res["map"] = pairs
+    # input coordinates away from knots and the clamp
+    pairs = []
+    while len(pairs) < 40:
+        a, yy, xx = int(g.integers(0, 3)), int(g.integers(0, H)), int(g.integers(0, W))
+        v = float(x[a, yy, xx])
+        q = v * (D - 1)
+        if not (2 * h < v < 1 - 2 * h) or abs(q - round(q)) <= 2 * h * (D - 1):
+            continue
+        vals = []
+        for sgn in (1, -1):
+            xx2 = x.astype(np.float64).copy(); xx2[a, yy, xx] = v + sgn * h
+            vals.append(loss_at(T, m, xx2, np.array([yy]), np.array([xx])))
+        pairs.append((out["dx"][b][a, yy, xx], (vals[0] - vals[1]) / (2 * h)))
+    res["x"] = pairs
+    for kind, pairs in res.items():
+        gp = np.array([p[0] for p in pairs]); fd = np.array([p[1] for p in pairs])
+        tol = 1e-3 * np.abs(fd).max() + 1e-2 * np.abs(fd)
+        bad = np.abs(gp - fd) > tol
+        assert not bad.any(), f"{kind}: {np.c_[gp[bad], fd[bad]][:5]}"

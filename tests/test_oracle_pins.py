@@ -467,3 +467,14 @@ def test_pair_is_degraded_and_deterministic():
     x2, t2 = op.make_pair(3, 64, 64)
     assert np.array_equal(x1, x2) and np.array_equal(t1, t2)
     assert 0.005 < np.abs(x1 - t1).mean() < 0.3
+
+
+def test_transform_at_matches_full_transform():
+    g = np.random.default_rng(20)
+    x = rand_image(g, 37, 53, -0.1, 1.1)
+    T = g.normal(size=(9, 9, 9))
+    m = g.uniform(size=(9, 5, 7))
+    full = ol.transform(x, T, m, [0.1, 0.2, 0.3])
+    ys = g.integers(0, 37, 200); xs = g.integers(0, 53, 200)
+    ys[:2] = [0, 36]; xs[:2] = [0, 52]
+    assert np.array_equal(ol.transform_at(x, T, m, ys, xs, [0.1, 0.2, 0.3]), full[:, ys, xs])
