@@ -1,12 +1,12 @@
 """Benchmark of the 2D-LUT hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows all|none|c1,c3,c4,c5]
 
 Headline (`value`): svdlut_apply on one 3840x2160 float32 frame (33x33 LUTs at rank 8,
-reconstruction fused, 480x270 spatial map), in Mpix/s, with inputs resident in HBM.
-Each timed step is one launch; four disjoint buffer sets rotate so that the 256 MB
-Infinity Cache cannot serve a step from the previous one.  The other hot-path rows are
-measured in the same run and reported under "rows".  Prints ONE JSON line.
+reconstruction fused, 480x270 spatial map), in Mpix/s, inputs resident in HBM.  Each timed
+step is one launch; four disjoint buffer sets rotate so that the 256 MB Infinity Cache
+cannot serve a step from the previous one.  The other hot-path rows are timed in the same
+run and reported under "rows".  Prints ONE JSON line.
 """
 from __future__ import annotations
 
@@ -22,6 +22,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_PEAK_TFLOPS = 2500.0
 N_ROT = 4
 
 
@@ -30,8 +31,8 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rows", default="all", help="comma list of extra rows to time (c1,c3,c4,c5) or 'none'")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline")
+    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline (0: skip)")
     return ap.parse_args()
 
 
@@ -48,6 +49,12 @@ def event_time(fn, steps, warmup, torch):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+def roof(bytes_alg, ms):
+    gbs = bytes_alg / (ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4)}
 
 
 def cpu_baseline(case, budget_s):
@@ -68,8 +75,120 @@ def cpu_baseline(case, budget_s):
         px += ys.size
         rows += min(band, H - y0)
         y0 += band
-    return {"value": px / t_total / 1e6, "unit": "Mpix/s", "cores": 1, "kind": "oracle",
-            "sample": f"{rows} of 2160 rows of the 3840x2160 frame (fp64 NumPy, single thread), {t_total:.1f} s"}
+    return {"value": round(px / t_total / 1e6, 3), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
+            "sample": f"{rows} of {H} rows of the {W}x{H} frame (fp64 NumPy, one thread), {t_total:.1f} s"}
+
+
+def row_c1(svd, torch, synth, args):
+    c = synth.plain_256()
+    d = [torch.from_numpy(a).cuda() for a in (c.x, c.U, c.s, c.V, c.smap)]
+    y = torch.empty_like(d[0])
+    ms = event_time(lambda i: svd.apply(*d, out=y), args.steps, args.warmup, torch)
+    return {"workload": "svdlut_apply 1x3x256x256 fp32, D=17 R=4, map 9x32x32", "ms": round(ms, 5),
+            "mpix_s": round(256 * 256 / (ms * 1e-3) / 1e6, 1)}
+
+
+def row_c3(svd, torch, synth, args):
+    images = synth.uneven_batch(64, workers=16)
+    xf, mf, U, s, V, descs = synth.pack_uneven(images)
+    del images
+    npx = sum(d["H"] * d["W"] for d in descs)
+    x = torch.from_numpy(xf).cuda().half()
+    m = torch.from_numpy(mf).cuda().half()
+    del xf, mf
+    y = torch.empty_like(x)
+    Ud, sd, Vd = (torch.from_numpy(a).cuda() for a in (U, s, V))
+    plan = svd.Plan(descs, 33, 8, torch.float16, torch.float16)
+    plan.autotune(x, y, Ud, sd, Vd, m)
+    steps = max(5, args.steps // 10)
+    ms = event_time(lambda i: plan.launch(x, y, Ud, sd, Vd, m), steps, 2, torch)
+    views = []
+    for b, d in enumerate(descs):
+        H, W, h, w = d["H"], d["W"], d["h"], d["w"]
+        views.append((x[d["x_off"]:d["x_off"] + 3 * H * W].view(1, 3, H, W), Ud[b:b + 1], sd[b:b + 1], Vd[b:b + 1],
+                      m[d["map_off"]:d["map_off"] + 9 * h * w].view(1, 9, h, w),
+                      y[d["y_off"]:d["y_off"] + 3 * H * W].view(1, 3, H, W)))
+
+    def loop(i):
+        for xv, u, ss, v, mv, yv in views:
+            svd.apply(xv, u, ss, v, mv, out=yv)
+
+    ms_loop = event_time(loop, steps, 2, torch)
+    bytes_alg = npx * 12 + sum(9 * d["h"] * d["w"] * 2 for d in descs) + 64 * 9 * (2 * 33 * 8 + 8) * 4
+    info = plan.info()
+    return {"workload": f"64 uneven images ({npx / 1e6:.1f} Mpx; 480x640/1080x1920/2160x3840 bases, +-10% width), "
+                        "fp16 storage, D=33 R=8, 1/8 maps, one graph-replayed persistent launch",
+            "ms": round(ms, 4), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1), "roofline": roof(bytes_alg, ms),
+            "loop_of_64_apply_ms": round(ms_loop, 4), "speedup_vs_loop": round(ms_loop / ms, 3),
+            "plan": {k: info[k] for k in ("block", "grid", "tuned", "graph")}}
+
+
+def row_c4(svd, torch, synth, args):
+    c = synth.diff_batch()
+    B, H, W = c.x.shape[0], c.x.shape[2], c.x.shape[3]
+    npx = B * H * W
+    sets = []
+    for k in range(N_ROT):
+        d = {a: torch.from_numpy(getattr(c, a)).cuda() for a in ("x", "U", "s", "V", "smap", "target")}
+        d["y"] = torch.empty_like(d["x"])
+        d["ws"] = svd.bwd_workspace(B, 33, "cuda")
+        sets.append(d)
+
+    def fwd(i):
+        d = sets[i % N_ROT]
+        svd.apply(d["x"], d["U"], d["s"], d["V"], d["smap"], out=d["y"])
+
+    def fwd_bwd(i):
+        d = sets[i % N_ROT]
+        svd.apply(d["x"], d["U"], d["s"], d["V"], d["smap"], out=d["y"])
+        _, dy = svd.loss(d["y"], d["target"], "l1")
+        svd.apply_bwd(d["x"], dy, d["U"], d["s"], d["V"], d["smap"], ws=d["ws"])
+
+    steps = max(5, args.steps // 4)
+    ms_f = event_time(fwd, steps, 3, torch)
+    ms_fb = event_time(fwd_bwd, steps, 3, torch)
+    # algorithmic bytes: forward 24.56 B/px; loss 24 B/px (y, target read, dy written);
+    # backward x 12 + dy 12 + dx 12 B/px plus the map and its gradient
+    mapb = B * 9 * 64 * 64 * 4
+    b_fwd = npx * 24 + mapb
+    b_fb = b_fwd + npx * 36 + npx * 36 + 2 * mapb
+    return {"workload": "16x3x512x512 fp32, D=33 R=8, map 9x64x64: apply + L1 loss + apply_bwd (dU ds dV dmap dx)",
+            "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4),
+            "fwd_mpix_s": round(npx / (ms_f * 1e-3) / 1e6, 1), "fwd_bwd_mpix_s": round(npx / (ms_fb * 1e-3) / 1e6, 1),
+            "fwd_roofline": roof(b_fwd, ms_f), "fwd_bwd_roofline": roof(b_fb, ms_fb)}
+
+
+def row_c5(svd, torch, synth, args):
+    from paper_2508_16121_amd import generator as G
+    g = np.random.default_rng(5)
+    x8 = torch.from_numpy(np.concatenate([synth.image(g, 2160, 3840)[None]] * 8)).cuda()
+    gen = G.Generator(33, 8, seed=0)
+    y = torch.empty_like(x8)
+
+    def infer(i):
+        U, s, V, m = gen.forward(x8)
+        svd.apply(x8, U, s, V, m, out=y)
+
+    steps = max(5, args.steps // 10)
+    ms_inf = event_time(infer, steps, 2, torch)
+    ms_gen = event_time(lambda i: gen.forward(x8), steps, 2, torch)
+    xb = torch.rand(16, 3, 256, 256, device="cuda")
+    tb = torch.rand(16, 3, 256, 256, device="cuda")
+    tr = G.Trainer(G.Generator(33, 8, seed=1), lr=1e-4)
+    ms_train = event_time(lambda i: tr.step(xb, tb), max(10, args.steps // 2), 3, torch)
+    macs = 0
+    ch = (3, 16, 32, 64, 128, 128)
+    for i in range(5):
+        hw = 256 >> (i + 1)
+        macs += hw * hw * ch[i + 1] * 9 * ch[i]
+    macs += 32 * 32 * 9 * 9 * 64 + 128 * 9 * (2 * 33 * 8 + 8)
+    tflops = 8 * 2 * macs / (ms_gen * 1e-3) / 1e12
+    return {"workload": "generator: 8x 3840x2160 fp32 -> downsample 256 -> 5 conv (bf16 MFMA) + map head + FC, "
+                        "then svdlut_apply at 4K; training step batch 16 at 256x256 (MSE, Adam lr 1e-4)",
+            "infer_ms_per_batch8": round(ms_inf, 4), "infer_mpix_s": round(8 * 3840 * 2160 / (ms_inf * 1e-3) / 1e6, 1),
+            "generator_fwd_ms_batch8": round(ms_gen, 4), "generator_mac_per_image": macs,
+            "generator_tflops": round(tflops, 3), "mfma_frac_of_bf16_peak": round(tflops / BF16_PEAK_TFLOPS, 6),
+            "train_step_ms_batch16": round(ms_train, 4), "train_steps_s": round(1000.0 / ms_train, 1)}
 
 
 def main():
@@ -97,18 +216,23 @@ def main():
 
     ms = event_time(step, args.steps, args.warmup, torch)
     bytes_alg = npx * (12 + 12) + 9 * h * w * 4 + 9 * D * R * 2 * 4 + 9 * R * 4
-    achieved = bytes_alg / (ms * 1e-3) / 1e9
-    value = npx / (ms * 1e-3) / 1e6
     out = {
         "metric": "Mpix/s of 2D-LUT apply at 4K (fwd, fwd+bwd, batched); % of HBM peak",
-        "value": round(value, 1), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32", "data": "synthetic",
+        "value": round(npx / (ms * 1e-3) / 1e6, 1), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms, 5), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "svdlut_apply 1x3x2160x3840 fp32, D=33 R=8, map 9x270x480 fp32, fused reconstruction",
                    "global_batch": 1, "pixels": npx},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None},
+        "roofline": dict(roof(bytes_alg, ms), traffic=None),
     }
+    want = {"c1", "c3", "c4", "c5"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
+    rows = {}
+    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5)):
+        if name in want:
+            rows[name] = fn(svd, torch, synth, args)
+            print(f"row {name} done", file=sys.stderr, flush=True)
+    if rows:
+        out["rows"] = rows
     out["cpu_baseline"] = cpu_baseline(c2, args.cpu_seconds) if args.cpu_seconds > 0 else None
     print(json.dumps(out), flush=True)
 

@@ -76,23 +76,20 @@ static svdlut_status check_dtype(svdlut_dtype t, const char* what) {
         if (st_ != SVDLUT_OK) return st_;         \
     } while (0)
 
-// Default launch shape of the fused apply: largest block whose LDS fits two workgroups per CU.
+// Default launch shape of the fused apply: one 1024-thread workgroup per CU (16 waves, the
+// most the kernel's register budget allows) when its LDS fits, else the largest that fits.
 static int default_block(int D, int R, int ncol_max, const DeviceInfo& di) {
-    const int cands[3] = {512, 1024, 256};
-    for (int b : cands) {
-        const size_t lds = apply_lds_bytes(D, R, b, ncol_max);
-        if (lds <= static_cast<size_t>(di.lds_per_block) && 2 * lds <= static_cast<size_t>(di.lds_per_cu))
-            return b;
-    }
-    for (int b : {256, 128, 64})
+    for (int b : {1024, 512, 256, 128, 64})
         if (apply_lds_bytes(D, R, b, ncol_max) <= static_cast<size_t>(di.lds_per_block)) return b;
     return 0;
 }
 
+// Workgroups per CU that can be resident: the kernel holds up to 128 VGPRs per lane, so a CU
+// fits 16 of its waves (4 per SIMD); LDS may allow fewer.
 static int blocks_per_cu(int D, int R, int block, int ncol_max, const DeviceInfo& di) {
     const size_t lds = apply_lds_bytes(D, R, block, ncol_max);
-    int by_lds = static_cast<int>(di.lds_per_cu / std::max<size_t>(lds, 1));
-    int by_waves = 32 / std::max(block / kWave, 1);
+    const int by_lds = static_cast<int>(di.lds_per_cu / std::max<size_t>(lds, 1));
+    const int by_waves = 16 / std::max(block / kWave, 1);
     return std::max(1, std::min(by_lds, by_waves));
 }
 

@@ -327,8 +327,17 @@ __global__ void __launch_bounds__(256) factor_grad_kernel(const float* __restric
     for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
         const int i = e / D, jj = e - (e / D) * D;
         const float* src = part + static_cast<size_t>(b) * gpi * nlut + lut_slot(p, i, jj, c, D);
+        // fixed summation order; eight independent loads in flight per step
         float acc = 0.f;
-        for (int g = 0; g < gpi; ++g) acc += src[static_cast<size_t>(g) * nlut];
+        int g = 0;
+        for (; g + 8 <= gpi; g += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[static_cast<size_t>(g + u) * nlut];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; g < gpi; ++g) acc += src[static_cast<size_t>(g) * nlut];
         dT[e] = acc;
     }
     for (int e = threadIdx.x; e < D * R; e += blockDim.x) { Us[e] = u[e]; Vs[e] = v[e]; }
@@ -360,7 +369,7 @@ __global__ void zero_kernel(float* p, int64_t n) {
 
 }  // namespace
 
-constexpr int kBwdPartials = 512;
+constexpr int kBwdPartials = 256;   // one workgroup per CU in a single round
 
 int bwd_groups_per_image(int B) { return std::max(1, kBwdPartials / std::max(B, 1)); }
 

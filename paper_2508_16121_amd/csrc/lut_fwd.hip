@@ -118,33 +118,49 @@ __device__ __forceinline__ void load_tile(const ApplyLaunch& a, const Geo& g, in
     }
 }
 
-// Stage the tile's map columns (rows iv and iv+1 blended with weight dv) into the wave's
-// region; returns the first staged column.
-template <typename MT>
-__device__ __forceinline__ int stage_map(const ApplyLaunch& a, const Geo& g, int iv, float dv, int xs,
-                                         float* stage) {
-    const int lane = threadIdx.x & (kWave - 1);
+// Map columns of the segment starting at xs: first staged column and count.
+__device__ __forceinline__ void seg_columns(const Geo& g, int xs, int& clo, int& ncols) {
     const int xlast = min(xs + kSeg, g.W) - 1;
-    const int iv1 = min(iv + 1, g.h - 1);
-    int clo, chi; uint32_t r;
+    int chi; uint32_t r;
     axis_left(g.ax, xs, clo, r);
     axis_left(g.ax, xlast, chi, r);
     chi = min(chi + 2, g.w - 1);
-    const int ncols = chi - clo + 1;
+    ncols = chi - clo + 1;
+}
+
+// Stage the raw map rows around a tile row for the segment's columns: per column the nine
+// channels of row iv ("top") and their difference to row iv+1 ("diff").  Rewritten only when
+// the wave moves to another segment or another pair of map rows.
+template <typename MT>
+__device__ __forceinline__ void stage_raw(const ApplyLaunch& a, const Geo& g, int iv, int clo, int ncols,
+                                          float* raw) {
+    const int lane = threadIdx.x & (kWave - 1);
+    const int iv1 = min(iv + 1, g.h - 1);
     const MT* m0 = reinterpret_cast<const MT*>(a.map) + g.map_off + static_cast<int64_t>(iv) * g.w + clo;
     const int64_t rowd = static_cast<int64_t>(iv1 - iv) * g.w;
     const int64_t mplane = static_cast<int64_t>(g.h) * g.w;
     for (int j = lane; j < ncols; j += kWave) {
-        float* dst = stage + j * kMapStride;
+        float* dst = raw + j * kRawStride;
         const MT* src = m0 + j;
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
             const float v0 = ldf<MT>(src + l * mplane);
             const float v1 = ldf<MT>(src + l * mplane + rowd);
-            dst[l] = fmaf(dv, v1 - v0, v0);
+            dst[l] = v0;
+            dst[9 + l] = v1 - v0;
         }
     }
-    return clo;
+}
+
+// Blend the staged rows for one tile row: stage[col][l] = top + dv * diff.
+__device__ __forceinline__ void blend_rows(const float* raw, float* stage, int ncols, float dv) {
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int j = lane; j < ncols; j += kWave) {
+        const float* src = raw + j * kRawStride;
+        float* dst = stage + j * kMapStride;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) dst[l] = fmaf(dv, src[9 + l], src[l]);
+    }
 }
 
 template <typename IO, bool FASTMAP, bool VEC>
@@ -228,7 +244,10 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
     store_px4<IO, VEC>(yout + 2 * plane, x0, g.W, out[2]);
 }
 
-// Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave contiguous runs.
+// Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave runs.  Inside an
+// image sub-range the tiles are walked column-major (same segment, consecutive rows), so a
+// wave keeps its staged raw map rows for about h/H of a map cell's height in pixel rows and
+// only re-reads the map from memory when the segment or the pair of map rows changes.
 template <typename IO, typename MT, bool FASTMAP>
 __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
     extern __shared__ float smem[];
@@ -237,7 +256,8 @@ __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
     float* aux = smem + lut_floats(D);
     const int nw = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave;
-    float* stage = aux + wave * a.ncol_max * kMapStride;
+    float* stage = aux + wave * a.ncol_max * (kMapStride + kRawStride);
+    float* raw = stage + a.ncol_max * kMapStride;
 
     const int G = gridDim.x;
     const int lb = logical_block(blockIdx.x, G);
@@ -250,47 +270,67 @@ __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
         const Geo g = image_geo(a, b, sizeof(IO));
         const int64_t img_end = g.tile0 + static_cast<int64_t>(g.H) * g.nseg;
         const int64_t te = min(t1, img_end);
-        // this wave's contiguous run of local tiles [w0, w0 + cnt)
-        const int n = static_cast<int>(te - t0);
-        const int q = (n + nw - 1) / nw;
-        const int w0 = static_cast<int>(t0 - g.tile0) + min(n, wave * q);
-        const int cnt = min(n, (wave + 1) * q) - min(n, wave * q);
-        int y = w0 / g.nseg;
-        int seg = w0 - y * g.nseg;
+        // local row-major tile range [ta, tb) of this image, walked column-major over its rows
+        const int ta = static_cast<int>(t0 - g.tile0);
+        const int tb = static_cast<int>(te - g.tile0);
+        const int ya = ta / g.nseg;
+        const int nr = (tb - 1) / g.nseg - ya + 1;
+        const int total = nr * g.nseg;
+        const int q = (total + nw - 1) / nw;
+        const int k0 = min(total, wave * q);
+        const int k1 = min(total, k0 + q);
+        // first valid tile of the run
+        int seg = k0 / nr, yr = k0 - seg * nr, k = k0;
+        auto valid = [&](int sg, int r) {
+            const int lt = (ya + r) * g.nseg + sg;
+            return lt >= ta && lt < tb;
+        };
+        auto advance = [&](int& sg, int& r, int& kk) {   // to the next valid tile (or kk == k1)
+            do {
+                ++kk;
+                if (++r == nr) { r = 0; ++sg; }
+            } while (kk < k1 && !valid(sg, r));
+        };
+        if (k < k1 && !valid(seg, yr)) advance(seg, yr, k);
         float px[3][4];
-        if (cnt > 0) load_tile<IO>(a, g, y, seg * kSeg, px);     // in flight during the LUT rebuild
+        if (k < k1) load_tile<IO>(a, g, ya + yr, seg * kSeg, px);   // in flight during the LUT rebuild
         const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
         stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R, kc);
         float bias3[3] = {0.f, 0.f, 0.f};
         if (a.bias) {
             bias3[0] = a.bias[3 * b]; bias3[1] = a.bias[3 * b + 1]; bias3[2] = a.bias[3 * b + 2];
         }
-        int iv = 0; uint32_t remv = 0;
-        axis_left(g.ay, y, iv, remv);
-        for (int k = 0; k < cnt; ++k) {
+        int st_seg = -1, st_iv = -1, clo = 0, ncols = 0;
+        while (k < k1) {
+            const int y = ya + yr;
             const int xs = seg * kSeg;
-            const float dv = static_cast<float>(remv) * g.ay.inv;
-            const int clo = stage_map<MT>(a, g, iv, dv, xs, stage);
-            // next tile of the run
-            int ny = y, nseg_i = seg + 1;
-            if (nseg_i == g.nseg) { nseg_i = 0; ++ny; }
+            int iv; uint32_t remv;
+            axis_left(g.ay, y, iv, remv);
+            if (seg != st_seg || iv != st_iv) {
+                seg_columns(g, xs, clo, ncols);
+                stage_raw<MT>(a, g, iv, clo, ncols, raw);
+                st_seg = seg;
+                st_iv = iv;
+                wave_sync();
+            }
+            blend_rows(raw, stage, ncols, static_cast<float>(remv) * g.ay.inv);
+            int nseg2 = seg, nyr = yr, nk = k;
+            advance(nseg2, nyr, nk);
             float nx[3][4];
-            if (k + 1 < cnt) load_tile<IO>(a, g, ny, nseg_i * kSeg, nx);
+            if (nk < k1) load_tile<IO>(a, g, ya + nyr, nseg2 * kSeg, nx);
             wave_sync();
             if (g.vec_ok && xs + kSeg <= g.W)
                 compute_tile<IO, FASTMAP, true>(a, g, Tl, stage, clo, D, y, xs, px, bias3);
             else
                 compute_tile<IO, FASTMAP, false>(a, g, Tl, stage, clo, D, y, xs, px, bias3);
             wave_sync();   // the stage region is rewritten for the next tile
-            if (k + 1 < cnt) {
+            if (nk < k1) {
 #pragma unroll
                 for (int c = 0; c < 3; ++c)
 #pragma unroll
                     for (int kk = 0; kk < 4; ++kk) px[c][kk] = nx[c][kk];
-                if (ny != y) axis_left(g.ay, ny, iv, remv);
-                y = ny;
-                seg = nseg_i;
             }
+            seg = nseg2; yr = nyr; k = nk;
         }
         t0 = te;
         __syncthreads();   // every wave is done with Tl and aux before the next image
@@ -313,7 +353,7 @@ size_t apply_lds_bytes(int D, int R, int block, int ncol_max) {
     const size_t lut = static_cast<size_t>(lut_floats(D));
     (void)R;
     const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
-    const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * kMapStride;
+    const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * (kMapStride + kRawStride);
     return sizeof(float) * (lut + std::max(scratch, stage));
 }
 
