@@ -33,6 +33,9 @@ def parse():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline (0: skip)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run device-to-device copies of one 4K fp32 frame (99.5 MB), the reference "
+                         "kernel that calibrates HBM byte counters in a profiler run")
     return ap.parse_args()
 
 
@@ -49,6 +52,33 @@ def event_time(fn, steps, warmup, torch):
     e1.record()
     torch.cuda.synchronize()
     return e0.elapsed_time(e1) / steps
+
+
+KERNEL_SOURCES = ("paper_2508_16121_amd/csrc/lut_fwd.hip", "paper_2508_16121_amd/csrc/lut_common.h",
+                  "paper_2508_16121_amd/csrc/internal.h")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_4k_fp32_traffic.json")
+
+
+def kernel_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch of the 4K apply from the committed counter summary, or None when
+    the kernel sources changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash():
+        return None
+    return t.get("bytes_per_launch")
 
 
 def roof(bytes_alg, ms):
@@ -223,8 +253,14 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "svdlut_apply 1x3x2160x3840 fp32, D=33 R=8, map 9x270x480 fp32, fused reconstruction",
                    "global_batch": 1, "pixels": npx},
-        "roofline": dict(roof(bytes_alg, ms), traffic=None),
+        "roofline": dict(roof(bytes_alg, ms), traffic=measured_traffic()),
     }
+    if args.copy_probe:
+        src = sets[0]["x"]
+        dst = torch.empty_like(src)
+        ms_copy = event_time(lambda i: dst.copy_(src), max(5, args.steps // 4), 2, torch)
+        out["copy_probe"] = {"bytes_per_copy": 2 * src.numel() * 4, "ms": round(ms_copy, 5),
+                             "gb_s": round(2 * src.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
     want = {"c1", "c3", "c4", "c5"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
     rows = {}
     for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5)):

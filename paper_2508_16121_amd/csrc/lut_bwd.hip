@@ -66,11 +66,15 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
     const MT* mb = reinterpret_cast<const MT*>(a.map) + static_cast<int64_t>(b) * 9 * mplane;
     for (int j = lane; j < ncols; j += kWave) {
         const int col = clo + j;
+        float v0[9], v1[9];
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {          // all eighteen loads in flight together
+            v0[l] = ldf<MT>(mb + l * mplane + static_cast<int64_t>(iv) * w + col);
+            v1[l] = ldf<MT>(mb + l * mplane + static_cast<int64_t>(iv1) * w + col);
+        }
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
-            const float v0 = ldf<MT>(mb + l * mplane + static_cast<int64_t>(iv) * w + col);
-            const float v1 = ldf<MT>(mb + l * mplane + static_cast<int64_t>(iv1) * w + col);
-            stage[j * kBwdStride + l] = fmaf(dv, v1 - v0, v0);
+            stage[j * kBwdStride + l] = fmaf(dv, v1[l] - v0[l], v0[l]);
             dstage[j * kBwdStride + l] = 0.f;
         }
     }

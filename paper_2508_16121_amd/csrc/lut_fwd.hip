@@ -140,15 +140,20 @@ __device__ __forceinline__ void stage_raw(const ApplyLaunch& a, const Geo& g, in
     const int64_t rowd = static_cast<int64_t>(iv1 - iv) * g.w;
     const int64_t mplane = static_cast<int64_t>(g.h) * g.w;
     for (int j = lane; j < ncols; j += kWave) {
-        float* dst = raw + j * kRawStride;
         const MT* src = m0 + j;
+        float v0[9], v1[9];
 #pragma unroll
-        for (int l = 0; l < 9; ++l) {
-            const float v0 = ldf<MT>(src + l * mplane);
-            const float v1 = ldf<MT>(src + l * mplane + rowd);
-            dst[l] = v0;
-            dst[9 + l] = v1 - v0;
+        for (int l = 0; l < 9; ++l) {          // all eighteen loads in flight together
+            v0[l] = ldf<MT>(src + l * mplane);
+            v1[l] = ldf<MT>(src + l * mplane + rowd);
         }
+        float* dst = raw + j * kRawStride;
+        *reinterpret_cast<float4*>(dst) = make_float4(v0[0], v0[1], v0[2], v0[3]);
+        *reinterpret_cast<float4*>(dst + 4) = make_float4(v0[4], v0[5], v0[6], v0[7]);
+        dst[8] = v0[8];
+        *reinterpret_cast<float4*>(dst + 12) = make_float4(v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2], v1[3] - v0[3]);
+        *reinterpret_cast<float4*>(dst + 16) = make_float4(v1[4] - v0[4], v1[5] - v0[5], v1[6] - v0[6], v1[7] - v0[7]);
+        dst[20] = v1[8] - v0[8];
     }
 }
 
@@ -157,9 +162,18 @@ __device__ __forceinline__ void blend_rows(const float* raw, float* stage, int n
     const int lane = threadIdx.x & (kWave - 1);
     for (int j = lane; j < ncols; j += kWave) {
         const float* src = raw + j * kRawStride;
+        const float4 t0 = *reinterpret_cast<const float4*>(src);
+        const float4 t1 = *reinterpret_cast<const float4*>(src + 4);
+        const float t2 = src[8];
+        const float4 d0 = *reinterpret_cast<const float4*>(src + 12);
+        const float4 d1 = *reinterpret_cast<const float4*>(src + 16);
+        const float d2 = src[20];
         float* dst = stage + j * kMapStride;
-#pragma unroll
-        for (int l = 0; l < 9; ++l) dst[l] = fmaf(dv, src[9 + l], src[l]);
+        *reinterpret_cast<float4*>(dst) =
+            make_float4(fmaf(dv, d0.x, t0.x), fmaf(dv, d0.y, t0.y), fmaf(dv, d0.z, t0.z), fmaf(dv, d0.w, t0.w));
+        *reinterpret_cast<float4*>(dst + 4) =
+            make_float4(fmaf(dv, d1.x, t1.x), fmaf(dv, d1.y, t1.y), fmaf(dv, d1.z, t1.z), fmaf(dv, d1.w, t1.w));
+        dst[8] = fmaf(dv, d2, t2);
     }
 }
 
@@ -301,7 +315,10 @@ __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
             bias3[0] = a.bias[3 * b]; bias3[1] = a.bias[3 * b + 1]; bias3[2] = a.bias[3 * b + 2];
         }
         int st_seg = -1, st_iv = -1, clo = 0, ncols = 0;
-        while (k < k1) {
+        // One tile: stage/blend the map, prefetch the next tile's pixels into `nxt`, compute
+        // the current tile from `cur`.  Two calls per iteration alternate the register sets,
+        // so the prefetched pixels are never copied.
+        auto do_tile = [&](float (&cur)[3][4], float (&nxt)[3][4]) {
             const int y = ya + yr;
             const int xs = seg * kSeg;
             int iv; uint32_t remv;
@@ -316,21 +333,20 @@ __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
             blend_rows(raw, stage, ncols, static_cast<float>(remv) * g.ay.inv);
             int nseg2 = seg, nyr = yr, nk = k;
             advance(nseg2, nyr, nk);
-            float nx[3][4];
-            if (nk < k1) load_tile<IO>(a, g, ya + nyr, nseg2 * kSeg, nx);
+            if (nk < k1) load_tile<IO>(a, g, ya + nyr, nseg2 * kSeg, nxt);
             wave_sync();
             if (g.vec_ok && xs + kSeg <= g.W)
-                compute_tile<IO, FASTMAP, true>(a, g, Tl, stage, clo, D, y, xs, px, bias3);
+                compute_tile<IO, FASTMAP, true>(a, g, Tl, stage, clo, D, y, xs, cur, bias3);
             else
-                compute_tile<IO, FASTMAP, false>(a, g, Tl, stage, clo, D, y, xs, px, bias3);
+                compute_tile<IO, FASTMAP, false>(a, g, Tl, stage, clo, D, y, xs, cur, bias3);
             wave_sync();   // the stage region is rewritten for the next tile
-            if (nk < k1) {
-#pragma unroll
-                for (int c = 0; c < 3; ++c)
-#pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) px[c][kk] = nx[c][kk];
-            }
             seg = nseg2; yr = nyr; k = nk;
+        };
+        float px2[3][4];
+        while (k < k1) {
+            do_tile(px, px2);
+            if (k >= k1) break;
+            do_tile(px2, px);
         }
         t0 = te;
         __syncthreads();   // every wave is done with Tl and aux before the next image
