@@ -11,6 +11,7 @@
 #include "lut_common.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace svdlut {
 
@@ -26,6 +27,7 @@ struct BwdDev {
     int mrows;          // map rows held per workgroup (0: flush dmap straight to global)
     int fast_map;
     int want_dT, want_dmap, want_dx, want_db;
+    int dt_copies;      // LDS copies of dT (lanes of odd index use the second copy when 2)
 };
 
 __device__ __forceinline__ void lds_add(float* p, float v) {
@@ -42,6 +44,7 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
     const BwdLaunch& a = P.a;
     const int lane = threadIdx.x & (kWave - 1);
     const int H = a.H, W = a.W, h = a.h, w = a.w, D = a.D;
+    const int dt_off = (P.dt_copies == 2 && (lane & 1)) ? lut_floats(D) : 0;
     const int nseg = (W + kSeg - 1) / kSeg;
     const int y = static_cast<int>(lt / nseg);
     const int seg = static_cast<int>(lt - static_cast<int64_t>(y) * nseg);
@@ -159,7 +162,7 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
                     const float T00 = t0[c], T01 = t0[3 + c], T10 = t1[c], T11 = t1[3 + c];
                     const float g = gy[c][k] * S[3 * c + p];
                     if (P.want_dT) {
-                        float* q0 = dTl + slot;
+                        float* q0 = dTl + slot + dt_off;
                         float* q1 = q0 + rowstep;
                         lds_add(q0 + c, g * w00);
                         lds_add(q1 + c, g * w10);
@@ -237,7 +240,7 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     const int nlut = lut_floats(D);
     float* Tl = smem;
     float* dTl = Tl + nlut;
-    float* macc = dTl + nlut;
+    float* macc = dTl + nlut * P.dt_copies;
     const int macc_n = P.mrows * 9 * a.w;
     float* aux = macc + ((macc_n + 3) & ~3);
     const int nw = blockDim.x / kWave;
@@ -263,7 +266,7 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
     stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R,
                min(a.R, 8));
-    for (int e = threadIdx.x; e < nlut; e += blockDim.x) dTl[e] = 0.f;
+    for (int e = threadIdx.x; e < nlut * P.dt_copies; e += blockDim.x) dTl[e] = 0.f;
     for (int e = threadIdx.x; e < macc_n; e += blockDim.x) macc[e] = 0.f;
     __syncthreads();
 
@@ -283,7 +286,8 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
 
     if (P.want_dT) {
         float* part = a.dT + (static_cast<size_t>(b) * P.gpi + j) * nlut;
-        for (int e = threadIdx.x; e < nlut; e += blockDim.x) part[e] = dTl[e];
+        for (int e = threadIdx.x; e < nlut; e += blockDim.x)
+            part[e] = P.dt_copies == 2 ? dTl[e] + dTl[nlut + e] : dTl[e];
     }
     if (P.want_dmap && P.mrows > 0 && t0 < t1) {
         const int64_t mplane = static_cast<int64_t>(a.h) * a.w;
@@ -382,12 +386,12 @@ size_t bwd_workspace_bytes(int B, int D) {
     return sizeof(float) * nlut * static_cast<size_t>(B) * bwd_groups_per_image(B);
 }
 
-static size_t bwd_lds(int D, int block, int ncol_max, int mrows, int w, int R) {
+static size_t bwd_lds(int D, int block, int ncol_max, int mrows, int w, int R, int copies) {
     const size_t nlut = static_cast<size_t>(lut_floats(D));
     const size_t macc = (static_cast<size_t>(mrows) * 9 * w + 3) & ~static_cast<size_t>(3);
     const size_t stage = static_cast<size_t>(block / kWave) * 2 * ncol_max * kBwdStride;
     const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
-    return sizeof(float) * (2 * nlut + macc + std::max(stage, scratch));
+    return sizeof(float) * ((1 + copies) * nlut + macc + std::max(stage, scratch));
 }
 
 svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
@@ -408,20 +412,28 @@ svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
     const int64_t band_rows = P.per / nseg + 2;
     const int64_t mr = (a.H > 1) ? (band_rows * (a.h - 1)) / (a.H - 1) + 3 : 1;
     int mrows = static_cast<int>(std::min<int64_t>(a.h, mr));
+    // Two LDS copies of dT (split by lane parity) halve same-address collisions of the
+    // atomics within one wave instruction when the LDS allows it; SVDLUT_BWD_DT_COPIES=1|2
+    // overrides the choice.
+    int copies = 2;
+    if (const char* e = std::getenv("SVDLUT_BWD_DT_COPIES")) copies = (std::atoi(e) == 1) ? 1 : 2;
+    if (!P.want_dT) copies = 1;
     int block = 0;
     const int blocks[2] = {512, 256};
-    for (int pass = 0; pass < 2 && block == 0; ++pass) {
+    for (int pass = 0; pass < 3 && block == 0; ++pass) {
         for (int bk : blocks) {
-            if (bwd_lds(a.D, bk, P.ncol_max, mrows, a.w, a.R) <= static_cast<size_t>(di.lds_per_block)) {
+            if (bwd_lds(a.D, bk, P.ncol_max, mrows, a.w, a.R, copies) <= static_cast<size_t>(di.lds_per_block)) {
                 block = bk;
                 break;
             }
         }
-        if (block == 0) mrows = 0;   // too many map columns: send dmap straight to global atomics
+        if (block == 0 && copies == 2) copies = 1;      // first give up the second dT copy
+        else if (block == 0) mrows = 0;                 // then send dmap straight to global atomics
     }
     if (block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply_bwd: map too wide for the LDS staging");
     P.mrows = P.want_dmap ? mrows : 0;
-    const size_t lds = bwd_lds(a.D, block, P.ncol_max, P.mrows, a.w, a.R);
+    P.dt_copies = copies;
+    const size_t lds = bwd_lds(a.D, block, P.ncol_max, P.mrows, a.w, a.R, copies);
 
     if (a.dmap) hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, a.dmap,
                                    static_cast<int64_t>(a.B) * 9 * a.h * a.w);
