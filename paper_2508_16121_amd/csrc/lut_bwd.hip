@@ -2,22 +2,34 @@
 //
 // Decomposition.  Each image gets `gpi` workgroups; workgroup j of image b processes a
 // contiguous band of row segments.  It rebuilds T into LDS, accumulates its share of dT
-// in a second LDS copy with LDS float atomics, and writes that copy to its own slot of a
-// partial buffer (plain stores).  A second kernel sums the gpi partials of each LUT in a
-// fixed order and applies the chain rule of T = U diag(s) V^T.  dmap contributions go
-// first to per-wave staged map columns, then to a workgroup copy of the map rows its
-// band touches (LDS atomics), then to global memory (one atomic per touched map element
-// per workgroup).  dx is written directly.
+// in a second LDS array, and writes that array to its own slot of a partial buffer (plain
+// stores).  A second kernel sums the gpi partials of each LUT in a fixed order and applies
+// the chain rule of T = U diag(s) V^T.  dmap contributions go first to per-wave staged map
+// columns, then to a workgroup copy of the map rows its band touches, then to global
+// memory (one atomic per touched map element per workgroup).  dx is written directly.
+//
+// Fixed-point LDS accumulation.  On gfx950 an LDS float atomic add costs about 200 cycles
+// per wave instruction whatever the addresses, an LDS integer add about 17 (measured), so
+// the LDS accumulators hold signed 32-bit fixed-point values.  Each workgroup first bounds
+// its contributions: every dT term is dy * S * w with |S| <= max|map| (S interpolates the
+// map) and 0 <= w <= 1, every dmap term is dy * phi * w with |phi| <= max|T|, and no entry
+// receives more than one term per pixel.  With N pixels in the band the scale is the
+// largest power of two 2^e with N * max|dy| * max|map| * 2^e < 2^30 (dT) and likewise with
+// max|T| (dmap), so no accumulator can overflow and every term is rounded to within
+// 2^-(e+1) of its value; the power-of-two scale makes the conversions exact apart from
+// that one rounding.  Integer sums are also independent of the order of the atomics.
+// Non-finite dy, map or T values (or bounds beyond the float range) make the workgroup
+// report NaN for its dT and dmap contributions.
 #include "lut_common.h"
 
 #include <algorithm>
-#include <cstdlib>
+#include <cfloat>
 
 namespace svdlut {
 
 namespace {
 
-constexpr int kBwdStride = 9;   // floats per staged map column in the backward
+constexpr int kBwdStride = 9;   // values per staged map column in the backward
 
 struct BwdDev {
     BwdLaunch a;
@@ -27,24 +39,36 @@ struct BwdDev {
     int mrows;          // map rows held per workgroup (0: flush dmap straight to global)
     int fast_map;
     int want_dT, want_dmap, want_dx, want_db;
-    int dt_copies;      // LDS copies of dT (lanes of odd index use the second copy when 2)
 };
 
-__device__ __forceinline__ void lds_add(float* p, float v) {
+__device__ __forceinline__ void lds_addi(int* p, int v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ void gbl_add(float* p, float v) {
     __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
+__device__ __forceinline__ int fix(float v) { return __float2int_rn(v); }
+
+// Largest power of two 2^e with n * m1 * m2 * 2^e < 2^30 (1 when a factor is 0); sets
+// `bad` when the bound does not fit the float exponent range.
+__device__ inline float fix_scale(float n, float m1, float m2, bool& bad) {
+    if (!(n > 0.f) || !(m1 > 0.f) || !(m2 > 0.f)) return 1.f;
+    int en, e1, e2;
+    frexpf(n, &en);
+    frexpf(m1, &e1);
+    frexpf(m2, &e2);
+    const int e = 30 - (en + e1 + e2);   // each factor f < 2^ef
+    if (e < -126) { bad = true; return 1.f; }
+    return ldexpf(1.f, min(e, 126));
+}
 
 template <typename IO, typename MT, bool FASTMAP, bool VEC>
 __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, const float* Tl,
-                                         float* dTl, float* macc, int row_lo, float* stage,
-                                         float* dstage, float (&dbsum)[3]) {
+                                         int* dTl, int* macc, int row_lo, float* stage,
+                                         int* dstage, float sT, float sM, float iM, float (&dbsum)[3]) {
     const BwdLaunch& a = P.a;
     const int lane = threadIdx.x & (kWave - 1);
     const int H = a.H, W = a.W, h = a.h, w = a.w, D = a.D;
-    const int dt_off = (P.dt_copies == 2 && (lane & 1)) ? lut_floats(D) : 0;
     const int nseg = (W + kSeg - 1) / kSeg;
     const int y = static_cast<int>(lt / nseg);
     const int seg = static_cast<int>(lt - static_cast<int64_t>(y) * nseg);
@@ -78,7 +102,7 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
             stage[j * kBwdStride + l] = fmaf(dv, v1[l] - v0[l], v0[l]);
-            dstage[j * kBwdStride + l] = 0.f;
+            dstage[j * kBwdStride + l] = 0;
         }
     }
     wave_sync();
@@ -162,12 +186,13 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
                     const float T00 = t0[c], T01 = t0[3 + c], T10 = t1[c], T11 = t1[3 + c];
                     const float g = gy[c][k] * S[3 * c + p];
                     if (P.want_dT) {
-                        float* q0 = dTl + slot + dt_off;
-                        float* q1 = q0 + rowstep;
-                        lds_add(q0 + c, g * w00);
-                        lds_add(q1 + c, g * w10);
-                        lds_add(q0 + 3 + c, g * w01);
-                        lds_add(q1 + 3 + c, g * w11);
+                        int* q0 = dTl + slot;
+                        int* q1 = q0 + rowstep;
+                        const float gs = g * sT;
+                        lds_addi(q0 + c, fix(gs * w00));
+                        lds_addi(q1 + c, fix(gs * w10));
+                        lds_addi(q0 + 3 + c, fix(gs * w01));
+                        lds_addi(q1 + 3 + c, fix(gs * w11));
                     }
                     gx[al] = fmaf(g, (1.f - db) * (T10 - T00) + db * (T11 - T01), gx[al]);
                     gx[be] = fmaf(g, (1.f - da) * (T01 - T00) + da * (T11 - T10), gx[be]);
@@ -183,8 +208,9 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
                             A1[l] = fmaf(gp, ta - tb, A1[l]);
                             A2[l] = fmaf(gp, tb, A2[l]);
                         } else {
-                            lds_add(dstage + jk * kBwdStride + l, gp * (1.f - du));
-                            lds_add(dstage + jk1 * kBwdStride + l, gp * du);
+                            const float gps = gp * sM;
+                            lds_addi(dstage + jk * kBwdStride + l, fix(gps * (1.f - du)));
+                            lds_addi(dstage + jk1 * kBwdStride + l, fix(gps * du));
                         }
                     }
                 }
@@ -198,9 +224,9 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
         if (FASTMAP && P.want_dmap) {
 #pragma unroll
             for (int l = 0; l < 9; ++l) {
-                lds_add(dstage + j0 * kBwdStride + l, A0[l]);
-                lds_add(dstage + j1 * kBwdStride + l, A1[l]);
-                lds_add(dstage + j2 * kBwdStride + l, A2[l]);
+                lds_addi(dstage + j0 * kBwdStride + l, fix(A0[l] * sM));
+                lds_addi(dstage + j1 * kBwdStride + l, fix(A1[l] * sM));
+                lds_addi(dstage + j2 * kBwdStride + l, fix(A2[l] * sM));
             }
         }
         if (P.want_dx) {
@@ -216,19 +242,56 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
             const int col = clo + j;
 #pragma unroll
             for (int l = 0; l < 9; ++l) {
-                const float v = dstage[j * kBwdStride + l];
-                const float v0 = v * (1.f - dv), v1 = v * dv;
+                const int v = dstage[j * kBwdStride + l];
+                if (v == 0) continue;
                 if (P.mrows > 0) {
-                    lds_add(macc + (l * P.mrows + (iv - row_lo)) * w + col, v0);
-                    if (iv1 != iv) lds_add(macc + (l * P.mrows + (iv1 - row_lo)) * w + col, v1);
+                    // exact split of the fixed-point column sum between the two rows
+                    const int v0 = fix(static_cast<float>(v) * (1.f - dv));
+                    lds_addi(macc + (l * P.mrows + (iv - row_lo)) * w + col, v0);
+                    if (iv1 != iv) lds_addi(macc + (l * P.mrows + (iv1 - row_lo)) * w + col, v - v0);
                 } else {
+                    const float fv = static_cast<float>(v) * iM;
                     float* dm = a.dmap + static_cast<int64_t>(b) * 9 * mplane + l * mplane;
-                    gbl_add(dm + static_cast<int64_t>(iv) * w + col, v0);
-                    if (iv1 != iv) gbl_add(dm + static_cast<int64_t>(iv1) * w + col, v1);
+                    gbl_add(dm + static_cast<int64_t>(iv) * w + col, fv * (1.f - dv));
+                    if (iv1 != iv) gbl_add(dm + static_cast<int64_t>(iv1) * w + col, fv * dv);
                 }
             }
         }
         wave_sync();
+    }
+}
+
+// max over the block of one value per thread (every thread gets the result); `red` holds
+// one float per wave and is free again when the function returns
+__device__ inline float block_max(float v, float* red) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    const int nw = blockDim.x / kWave;
+    __syncthreads();
+    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
+    __syncthreads();
+    float m = red[0];
+    for (int i = 1; i < nw; ++i) m = fmaxf(m, red[i]);
+    __syncthreads();
+    return m;
+}
+
+template <typename T>
+__device__ inline void absmax_range(const T* p, int64_t n, float& m, bool& bad) {
+    int64_t i = threadIdx.x;
+    for (; i + 3 * static_cast<int64_t>(blockDim.x) < n; i += 4 * static_cast<int64_t>(blockDim.x)) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = fabsf(ldf<T>(p + i + u * static_cast<int64_t>(blockDim.x)));
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            bad |= !(v[u] <= FLT_MAX);
+            m = fmaxf(m, v[u]);
+        }
+    }
+    for (; i < n; i += blockDim.x) {
+        const float v = fabsf(ldf<T>(p + i));
+        bad |= !(v <= FLT_MAX);
+        m = fmaxf(m, v);
     }
 }
 
@@ -239,14 +302,14 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     const int D = a.D;
     const int nlut = lut_floats(D);
     float* Tl = smem;
-    float* dTl = Tl + nlut;
-    float* macc = dTl + nlut * P.dt_copies;
+    int* dTl = reinterpret_cast<int*>(Tl + nlut);
+    int* macc = dTl + nlut;
     const int macc_n = P.mrows * 9 * a.w;
-    float* aux = macc + ((macc_n + 3) & ~3);
+    float* aux = reinterpret_cast<float*>(macc + ((macc_n + 3) & ~3));
     const int nw = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave;
     float* stage = aux + wave * 2 * P.ncol_max * kBwdStride;
-    float* dstage = stage + P.ncol_max * kBwdStride;
+    int* dstage = reinterpret_cast<int*>(stage + P.ncol_max * kBwdStride);
 
     const int lb = logical_block(blockIdx.x, gridDim.x);
     const int b = lb / P.gpi;
@@ -257,37 +320,78 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     const int64_t t1 = min(tpi, t0 + P.per);
 
     // map rows this band touches
-    int row_lo = 0;
+    int row_lo = 0, row_hi = -1;
     if (t0 < t1) {
         const AxisMap ay = make_axis(a.H, a.h);
         uint32_t r;
         axis_left(ay, static_cast<int>(t0 / nseg), row_lo, r);
+        axis_left(ay, static_cast<int>((t1 - 1) / nseg), row_hi, r);
+        row_hi = min(row_hi + 1, a.h - 1);
     }
     const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
     stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R,
                min(a.R, 8));
-    for (int e = threadIdx.x; e < nlut * P.dt_copies; e += blockDim.x) dTl[e] = 0.f;
-    for (int e = threadIdx.x; e < macc_n; e += blockDim.x) macc[e] = 0.f;
+    for (int e = threadIdx.x; e < nlut; e += blockDim.x) dTl[e] = 0;
+    for (int e = threadIdx.x; e < macc_n; e += blockDim.x) macc[e] = 0;
     __syncthreads();
 
-    float dbsum[3] = {0.f, 0.f, 0.f};
+    // bounds of the band's contributions -> fixed-point scales
     const int64_t plane = static_cast<int64_t>(a.H) * a.W;
+    float sT = 1.f, sM = 1.f;
+    bool bad = false;
+    if ((P.want_dT || P.want_dmap) && t0 < t1) {
+        float mdy = 0.f, mmap = 0.f, mT = 0.f;
+        bool nf = false;
+        const int64_t e0 = (t0 / nseg) * a.W + (t0 % nseg) * kSeg;
+        const int64_t e1 = ((t1 - 1) / nseg) * a.W + min(((t1 - 1) % nseg) * kSeg + kSeg, static_cast<int64_t>(a.W));
+        const IO* dyb = reinterpret_cast<const IO*>(a.dy) + static_cast<int64_t>(b) * 3 * plane;
+        for (int c = 0; c < 3; ++c) absmax_range<IO>(dyb + c * plane + e0, e1 - e0, mdy, nf);
+        if (P.want_dT) {
+            const int64_t mplane = static_cast<int64_t>(a.h) * a.w;
+            const MT* mb = reinterpret_cast<const MT*>(a.map) + static_cast<int64_t>(b) * 9 * mplane +
+                           static_cast<int64_t>(row_lo) * a.w;
+            for (int l = 0; l < 9; ++l)
+                absmax_range<MT>(mb + l * mplane, static_cast<int64_t>(row_hi - row_lo + 1) * a.w, mmap, nf);
+        }
+        if (P.want_dmap) {
+            const int RS = lut_row_stride(D), PS = lut_pair_stride(D);
+            for (int e = threadIdx.x; e < 9 * D * D; e += blockDim.x) {
+                const int l = e / (D * D), r = e - l * (D * D);
+                const int i = r / D, jj = r - i * D;
+                const float v = fabsf(Tl[(l % 3) * PS + i * RS + 3 * jj + l / 3]);
+                nf |= !(v <= FLT_MAX);
+                mT = fmaxf(mT, v);
+            }
+        }
+        mdy = block_max(mdy, aux);
+        mmap = block_max(mmap, aux);
+        mT = block_max(mT, aux);
+        bad = block_max(nf ? 1.f : 0.f, aux) > 0.f;
+        const float n = static_cast<float>((t1 - t0) * kSeg);
+        sT = fix_scale(n, mdy, mmap, bad);
+        sM = fix_scale(n, mdy, mT, bad);
+    }
+    const float iT = 1.f / sT, iM = 1.f / sM;
+
+    float dbsum[3] = {0.f, 0.f, 0.f};
     const bool base_ok = ((plane | a.W) & 3) == 0 &&
                          ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.dy) |
                            reinterpret_cast<uintptr_t>(a.dx)) & (4 * sizeof(IO) - 1)) == 0;
     for (int64_t t = t0 + wave; t < t1; t += nw) {
         const int xs = static_cast<int>(t % nseg) * kSeg;
         if (base_ok && xs + kSeg <= a.W)
-            bwd_tile<IO, MT, FASTMAP, true>(P, b, t, Tl, dTl, macc, row_lo, stage, dstage, dbsum);
+            bwd_tile<IO, MT, FASTMAP, true>(P, b, t, Tl, dTl, macc, row_lo, stage, dstage, sT, sM,
+                                            bad ? __builtin_nanf("") : iM, dbsum);
         else
-            bwd_tile<IO, MT, FASTMAP, false>(P, b, t, Tl, dTl, macc, row_lo, stage, dstage, dbsum);
+            bwd_tile<IO, MT, FASTMAP, false>(P, b, t, Tl, dTl, macc, row_lo, stage, dstage, sT, sM,
+                                             bad ? __builtin_nanf("") : iM, dbsum);
     }
     __syncthreads();
 
     if (P.want_dT) {
         float* part = a.dT + (static_cast<size_t>(b) * P.gpi + j) * nlut;
         for (int e = threadIdx.x; e < nlut; e += blockDim.x)
-            part[e] = P.dt_copies == 2 ? dTl[e] + dTl[nlut + e] : dTl[e];
+            part[e] = bad ? __builtin_nanf("") : static_cast<float>(dTl[e]) * iT;
     }
     if (P.want_dmap && P.mrows > 0 && t0 < t1) {
         const int64_t mplane = static_cast<int64_t>(a.h) * a.w;
@@ -296,10 +400,11 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
             const int rr = (e / a.w) % P.mrows;
             const int col = e % a.w;
             const int row = row_lo + rr;
-            const float v = macc[e];
-            if (row < a.h && v != 0.f)
+            const int v = macc[e];
+            if (row < a.h && (v != 0 || bad))
                 gbl_add(a.dmap + static_cast<int64_t>(b) * 9 * mplane + l * mplane +
-                            static_cast<int64_t>(row) * a.w + col, v);
+                            static_cast<int64_t>(row) * a.w + col,
+                        bad ? __builtin_nanf("") : static_cast<float>(v) * iM);
         }
     }
     if (P.want_db) {
@@ -386,12 +491,16 @@ size_t bwd_workspace_bytes(int B, int D) {
     return sizeof(float) * nlut * static_cast<size_t>(B) * bwd_groups_per_image(B);
 }
 
-static size_t bwd_lds(int D, int block, int ncol_max, int mrows, int w, int R, int copies) {
+// LDS of the backward: T (float) and dT (int32), the map-row accumulator (int32), and per
+// wave a staged map (float) plus its gradient (int32); the LUT rebuild scratch and the
+// block reductions reuse the staging area.
+static size_t bwd_lds(int D, int block, int ncol_max, int mrows, int w, int R) {
+    (void)R;
     const size_t nlut = static_cast<size_t>(lut_floats(D));
     const size_t macc = (static_cast<size_t>(mrows) * 9 * w + 3) & ~static_cast<size_t>(3);
     const size_t stage = static_cast<size_t>(block / kWave) * 2 * ncol_max * kBwdStride;
     const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
-    return sizeof(float) * ((1 + copies) * nlut + macc + std::max(stage, scratch));
+    return sizeof(float) * (2 * nlut + macc + std::max(stage, scratch));
 }
 
 svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
@@ -412,28 +521,20 @@ svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
     const int64_t band_rows = P.per / nseg + 2;
     const int64_t mr = (a.H > 1) ? (band_rows * (a.h - 1)) / (a.H - 1) + 3 : 1;
     int mrows = static_cast<int>(std::min<int64_t>(a.h, mr));
-    // Two LDS copies of dT (split by lane parity) halve same-address collisions of the
-    // atomics within one wave instruction when the LDS allows it; SVDLUT_BWD_DT_COPIES=1|2
-    // overrides the choice.
-    int copies = 2;
-    if (const char* e = std::getenv("SVDLUT_BWD_DT_COPIES")) copies = (std::atoi(e) == 1) ? 1 : 2;
-    if (!P.want_dT) copies = 1;
     int block = 0;
     const int blocks[2] = {512, 256};
-    for (int pass = 0; pass < 3 && block == 0; ++pass) {
+    for (int pass = 0; pass < 2 && block == 0; ++pass) {
         for (int bk : blocks) {
-            if (bwd_lds(a.D, bk, P.ncol_max, mrows, a.w, a.R, copies) <= static_cast<size_t>(di.lds_per_block)) {
+            if (bwd_lds(a.D, bk, P.ncol_max, mrows, a.w, a.R) <= static_cast<size_t>(di.lds_per_block)) {
                 block = bk;
                 break;
             }
         }
-        if (block == 0 && copies == 2) copies = 1;      // first give up the second dT copy
-        else if (block == 0) mrows = 0;                 // then send dmap straight to global atomics
+        if (block == 0) mrows = 0;   // too many map columns: send dmap straight to global atomics
     }
     if (block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply_bwd: map too wide for the LDS staging");
     P.mrows = P.want_dmap ? mrows : 0;
-    P.dt_copies = copies;
-    const size_t lds = bwd_lds(a.D, block, P.ncol_max, P.mrows, a.w, a.R, copies);
+    const size_t lds = bwd_lds(a.D, block, P.ncol_max, P.mrows, a.w, a.R);
 
     if (a.dmap) hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, a.dmap,
                                    static_cast<int64_t>(a.B) * 9 * a.h * a.w);
