@@ -62,55 +62,34 @@ __device__ inline float fix_scale(float n, float m1, float m2, bool& bad) {
     return ldexpf(1.f, min(e, 126));
 }
 
+// Geometry shared by all tiles of a workgroup.
+struct BwdGeo {
+    AxisMap ax, ay;
+    int nseg;
+    int64_t plane, mplane;
+};
+
+// One tile (row y, 256-pixel segment seg) of the backward.  The staged raw map rows (the
+// nine channels of rows iv and iv+1 for the segment's columns) are kept per wave and only
+// reloaded when the wave moves to another segment or another pair of map rows.
 template <typename IO, typename MT, bool FASTMAP, bool VEC>
-__device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, const float* Tl,
-                                         int* dTl, int* macc, int row_lo, float* stage,
-                                         int* dstage, float sT, float sM, float iM, float (&dbsum)[3]) {
+__device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b, int y, int seg,
+                                         const float* Tl, int* dTl, int* macc, int row_lo,
+                                         float* raw, float* stage, int* dstage, int& st_seg, int& st_iv,
+                                         float sT, float sM, float iM, float (&dbsum)[3]) {
     const BwdLaunch& a = P.a;
     const int lane = threadIdx.x & (kWave - 1);
     const int H = a.H, W = a.W, h = a.h, w = a.w, D = a.D;
-    const int nseg = (W + kSeg - 1) / kSeg;
-    const int y = static_cast<int>(lt / nseg);
-    const int seg = static_cast<int>(lt - static_cast<int64_t>(y) * nseg);
+    (void)H;
     const int xs = seg * kSeg;
     const int x0 = xs + lane * kPxPerLane;
     const int xlast = min(xs + kSeg, W) - 1;
-
-    const AxisMap ay = make_axis(H, h);
-    int iv; uint32_t remv;
-    axis_left(ay, y, iv, remv);
-    const float dv = static_cast<float>(remv) * ay.inv;
-    const int iv1 = min(iv + 1, h - 1);
-    const AxisMap ax = make_axis(W, w);
-    int clo; uint32_t rlo;
-    axis_left(ax, xs, clo, rlo);
-    int chi; uint32_t rhi;
-    axis_left(ax, xlast, chi, rhi);
-    chi = min(chi + 2, w - 1);
-    const int ncols = chi - clo + 1;
-
-    const int64_t mplane = static_cast<int64_t>(h) * w;
-    const MT* mb = reinterpret_cast<const MT*>(a.map) + static_cast<int64_t>(b) * 9 * mplane;
-    for (int j = lane; j < ncols; j += kWave) {
-        const int col = clo + j;
-        float v0[9], v1[9];
-#pragma unroll
-        for (int l = 0; l < 9; ++l) {          // all eighteen loads in flight together
-            v0[l] = ldf<MT>(mb + l * mplane + static_cast<int64_t>(iv) * w + col);
-            v1[l] = ldf<MT>(mb + l * mplane + static_cast<int64_t>(iv1) * w + col);
-        }
-#pragma unroll
-        for (int l = 0; l < 9; ++l) {
-            stage[j * kBwdStride + l] = fmaf(dv, v1[l] - v0[l], v0[l]);
-            dstage[j * kBwdStride + l] = 0;
-        }
-    }
-    wave_sync();
-
-    const int64_t plane = static_cast<int64_t>(H) * W;
+    const int64_t plane = G.plane;
     const int64_t img = static_cast<int64_t>(b) * 3 * plane + static_cast<int64_t>(y) * W;
+
+    // the pixel loads go first: their latency overlaps the map staging below
+    float px[3][4], gy[3][4];
     if (x0 < W) {
-        float px[3][4], gy[3][4], dx[3][4];
         const IO* xin = reinterpret_cast<const IO*>(a.x) + img;
         const IO* gin = reinterpret_cast<const IO*>(a.dy) + img;
 #pragma unroll
@@ -118,11 +97,61 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
             load_px4<IO, VEC>(xin + c * plane, x0, W, px[c]);
             load_px4<IO, VEC>(gin + c * plane, x0, W, gy[c]);
         }
+    }
+
+    int iv; uint32_t remv;
+    axis_left(G.ay, y, iv, remv);
+    const float dv = static_cast<float>(remv) * G.ay.inv;
+    const int iv1 = min(iv + 1, h - 1);
+    int clo; uint32_t rlo;
+    axis_left(G.ax, xs, clo, rlo);
+    int chi; uint32_t rhi;
+    axis_left(G.ax, xlast, chi, rhi);
+    chi = min(chi + 2, w - 1);
+    const int ncols = chi - clo + 1;
+    const int64_t mplane = G.mplane;
+
+    if (seg != st_seg || iv != st_iv) {
+        const MT* m0 = reinterpret_cast<const MT*>(a.map) + static_cast<int64_t>(b) * 9 * mplane +
+                       static_cast<int64_t>(iv) * w + clo;
+        const int64_t rowd = static_cast<int64_t>(iv1 - iv) * w;
+        for (int j = lane; j < ncols; j += kWave) {
+            float v0[9], v1[9];
+#pragma unroll
+            for (int l = 0; l < 9; ++l) {      // all eighteen loads in flight together
+                v0[l] = ldf<MT>(m0 + l * mplane + j);
+                v1[l] = ldf<MT>(m0 + l * mplane + rowd + j);
+            }
+            float* dst = raw + j * kRawStride;
+#pragma unroll
+            for (int l = 0; l < 9; ++l) {
+                dst[l] = v0[l];
+                dst[12 + l] = v1[l] - v0[l];
+            }
+        }
+        st_seg = seg;
+        st_iv = iv;
+        wave_sync();
+    }
+    for (int j = lane; j < ncols; j += kWave) {
+        const float* src = raw + j * kRawStride;
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            stage[j * kBwdStride + l] = fmaf(dv, src[12 + l], src[l]);
+            dstage[j * kBwdStride + l] = 0;
+        }
+    }
+    wave_sync();
+
+    if (x0 < W) {
+        float dx[3][4];
+        const AxisMap& ax = G.ax;
         int c0; uint32_t rem0;
         axis_left(ax, x0, c0, rem0);
         const float Dm1 = static_cast<float>(D - 1);
         const int Dm2 = D - 2;
         const int rowstep = lut_row_stride(D);
+        const int pairstep = lut_pair_stride(D);
 
         float r0[9], d01[9], d12[9], A0[9], A1[9], A2[9];
         const int j0 = c0 - clo;
@@ -178,7 +207,7 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, int b, int64_t lt, con
                 const float w10 = da - w11;
                 const float w01 = db - w11;
                 const float w00 = 1.f - da - db + w11;
-                const int slot = lut_slot(p, ii[al], ii[be], 0, D);
+                const int slot = p * pairstep + ii[al] * rowstep + 3 * ii[be];
                 const float* t0 = Tl + slot;
                 const float* t1 = t0 + rowstep;
 #pragma unroll
@@ -275,24 +304,38 @@ __device__ inline float block_max(float v, float* red) {
     return m;
 }
 
+__device__ __forceinline__ void absmax_acc(float v, float& m, bool& bad) {
+    v = fabsf(v);
+    bad |= !(v <= FLT_MAX);
+    m = fmaxf(m, v);
+}
+
+// max |p[i]| over [0, n) by the whole block: 4-element vector loads (eight per thread in
+// flight) when p is aligned to 4 elements, element loads for the rest
 template <typename T>
 __device__ inline void absmax_range(const T* p, int64_t n, float& m, bool& bad) {
-    int64_t i = threadIdx.x;
-    for (; i + 3 * static_cast<int64_t>(blockDim.x) < n; i += 4 * static_cast<int64_t>(blockDim.x)) {
-        float v[4];
+    int64_t i0 = 0;
+    if ((reinterpret_cast<uintptr_t>(p) & (4 * sizeof(T) - 1)) == 0) {
+        const int64_t n4 = n / 4, step = blockDim.x;
+        int64_t v = threadIdx.x;
+        for (; v + 7 * step < n4; v += 8 * step) {
+            float q[8][4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) v[u] = fabsf(ldf<T>(p + i + u * static_cast<int64_t>(blockDim.x)));
+            for (int u = 0; u < 8; ++u) ld4<T>(p + 4 * (v + u * step), q[u]);
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            bad |= !(v[u] <= FLT_MAX);
-            m = fmaxf(m, v[u]);
+            for (int u = 0; u < 8; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) absmax_acc(q[u][e], m, bad);
         }
+        for (; v < n4; v += step) {
+            float q[4];
+            ld4<T>(p + 4 * v, q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) absmax_acc(q[e], m, bad);
+        }
+        i0 = n4 * 4;
     }
-    for (; i < n; i += blockDim.x) {
-        const float v = fabsf(ldf<T>(p + i));
-        bad |= !(v <= FLT_MAX);
-        m = fmaxf(m, v);
-    }
+    for (int64_t i = i0 + threadIdx.x; i < n; i += blockDim.x) absmax_acc(ldf<T>(p + i), m, bad);
 }
 
 template <typename IO, typename MT, bool FASTMAP>
@@ -308,7 +351,8 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     float* aux = reinterpret_cast<float*>(macc + ((macc_n + 3) & ~3));
     const int nw = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave;
-    float* stage = aux + wave * 2 * P.ncol_max * kBwdStride;
+    float* raw = aux + wave * P.ncol_max * (kRawStride + 2 * kBwdStride);
+    float* stage = raw + P.ncol_max * kRawStride;
     int* dstage = reinterpret_cast<int*>(stage + P.ncol_max * kBwdStride);
 
     const int lb = logical_block(blockIdx.x, gridDim.x);
@@ -377,14 +421,35 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     const bool base_ok = ((plane | a.W) & 3) == 0 &&
                          ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.dy) |
                            reinterpret_cast<uintptr_t>(a.dx)) & (4 * sizeof(IO) - 1)) == 0;
-    for (int64_t t = t0 + wave; t < t1; t += nw) {
-        const int xs = static_cast<int>(t % nseg) * kSeg;
-        if (base_ok && xs + kSeg <= a.W)
-            bwd_tile<IO, MT, FASTMAP, true>(P, b, t, Tl, dTl, macc, row_lo, stage, dstage, sT, sM,
-                                            bad ? __builtin_nanf("") : iM, dbsum);
-        else
-            bwd_tile<IO, MT, FASTMAP, false>(P, b, t, Tl, dTl, macc, row_lo, stage, dstage, sT, sM,
-                                             bad ? __builtin_nanf("") : iM, dbsum);
+    if (t0 < t1) {
+        BwdGeo G;
+        G.ax = make_axis(a.W, a.w);
+        G.ay = make_axis(a.H, a.h);
+        G.nseg = nseg;
+        G.plane = plane;
+        G.mplane = static_cast<int64_t>(a.h) * a.w;
+        const float iMx = bad ? __builtin_nanf("") : iM;
+        // The band's rows [ya, yb] x segments, walked column-major (same segment, consecutive
+        // rows) in one contiguous run per wave, so the staged map rows are reused.
+        const int ya = static_cast<int>(t0 / nseg);
+        const int nr = static_cast<int>((t1 - 1) / nseg) - ya + 1;
+        const int total = nr * nseg;
+        const int q = (total + nw - 1) / nw;
+        const int k0 = min(total, wave * q);
+        const int k1 = min(total, k0 + q);
+        int st_seg = -1, st_iv = -1;
+        for (int k = k0; k < k1; ++k) {
+            const int seg = k / nr;
+            const int y = ya + (k - seg * nr);
+            const int64_t lt = static_cast<int64_t>(y) * nseg + seg;
+            if (lt < t0 || lt >= t1) continue;
+            if (base_ok && seg * kSeg + kSeg <= a.W)
+                bwd_tile<IO, MT, FASTMAP, true>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage, dstage,
+                                                st_seg, st_iv, sT, sM, iMx, dbsum);
+            else
+                bwd_tile<IO, MT, FASTMAP, false>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage, dstage,
+                                                 st_seg, st_iv, sT, sM, iMx, dbsum);
+        }
     }
     __syncthreads();
 
@@ -492,13 +557,13 @@ size_t bwd_workspace_bytes(int B, int D) {
 }
 
 // LDS of the backward: T (float) and dT (int32), the map-row accumulator (int32), and per
-// wave a staged map (float) plus its gradient (int32); the LUT rebuild scratch and the
-// block reductions reuse the staging area.
+// wave the raw map rows, the blended map row (float) and its gradient (int32); the LUT
+// rebuild scratch and the block reductions reuse the staging area.
 static size_t bwd_lds(int D, int block, int ncol_max, int mrows, int w, int R) {
     (void)R;
     const size_t nlut = static_cast<size_t>(lut_floats(D));
     const size_t macc = (static_cast<size_t>(mrows) * 9 * w + 3) & ~static_cast<size_t>(3);
-    const size_t stage = static_cast<size_t>(block / kWave) * 2 * ncol_max * kBwdStride;
+    const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * (kRawStride + 2 * kBwdStride);
     const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
     return sizeof(float) * (2 * nlut + macc + std::max(stage, scratch));
 }

@@ -96,9 +96,9 @@ __device__ __forceinline__ void decode(float xv, float Dm1, int Dm2, int& i, flo
 // then maps to nine distinct LDS banks whether the LDS is viewed as 32 or 64 banks, which
 // matters because per-pixel noise scatters neighbouring pixels over adjacent cells.
 __host__ __device__ inline int lut_row_stride(int D) {
-    int rs = 3 * D;
-    while ((rs & 31) != 10 && (rs & 31) != 22) ++rs;
-    return rs;
+    // 3D rounded up to the next value that is 10 or 22 modulo 32 (closed form, no loop)
+    const int rs = 3 * D, r = rs & 31;
+    return rs + (r <= 10 ? 10 - r : (r <= 22 ? 22 - r : 42 - r));
 }
 __host__ __device__ inline int lut_pair_stride(int D) { return D * lut_row_stride(D); }
 __host__ __device__ inline int lut_floats(int D) { return (3 * lut_pair_stride(D) + 3) & ~3; }
