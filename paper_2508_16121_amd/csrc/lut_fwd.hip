@@ -45,8 +45,7 @@ svdlut_status launch_reconstruct(const float* U, const float* s, const float* V,
 // wave (4 consecutive pixels per lane).  Tiles are numbered image-major, row-major.  Each
 // workgroup takes a contiguous chunk of tiles; within each image the chunk is split into
 // contiguous per-wave runs.  Before the first tile of an image the workgroup rebuilds that
-// image's LUTs into LDS; each wave's first pixel loads are already in flight by then, and
-// every tile's loads are issued one tile ahead.
+// image's LUTs into LDS.
 //
 // Spatial map: per tile the wave stages, for every map column the segment touches, the
 // nine map channels blended between the two map rows around the tile's row
@@ -102,20 +101,17 @@ __device__ __forceinline__ int image_of_tile(const ApplyLaunch& a, int64_t t) {
     return lo;
 }
 
-// Pixels of the lane for the tile at row y, segment start xs: 3 channels x 4 pixels.
-template <typename IO>
+// Pixels of the lane for the tile at row y, segment start xs: 3 channels x 4 pixels.  VEC
+// (rows 4-element aligned): one vector load per channel, lanes past the row end re-read
+// the row's last four pixels; otherwise element loads with the index clamped to the row.
+template <typename IO, bool VEC>
 __device__ __forceinline__ void load_tile(const ApplyLaunch& a, const Geo& g, int y, int xs, float (&px)[3][4]) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int x0 = min(xs + lane * kPxPerLane, g.W - 1);
+    const int x0 = min(xs + lane * kPxPerLane, VEC ? g.W - kPxPerLane : g.W - 1);
     const int64_t plane = static_cast<int64_t>(g.H) * g.W;
     const IO* xin = reinterpret_cast<const IO*>(a.x) + g.x_off + static_cast<int64_t>(y) * g.W;
-    if (g.vec_ok && xs + kSeg <= g.W) {
 #pragma unroll
-        for (int c = 0; c < 3; ++c) load_px4<IO, true>(xin + c * plane, x0, g.W, px[c]);
-    } else {
-#pragma unroll
-        for (int c = 0; c < 3; ++c) load_px4<IO, false>(xin + c * plane, x0, g.W, px[c]);
-    }
+    for (int c = 0; c < 3; ++c) load_px4<IO, VEC>(xin + c * plane, x0, g.W, px[c]);
 }
 
 // Map columns of the segment starting at xs: first staged column and count.
@@ -181,15 +177,19 @@ template <typename IO, bool FASTMAP, bool VEC>
 __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g, const float* Tl,
                                              const float* stage, int clo, int D, int y, int xs,
                                              const float (&px)[3][4], const float (&bias3)[3]) {
+    // Lanes past the row end work on the row's last pixels (the same x0 as load_tile) and
+    // store the same values again, so every lane issues the same loads and stores.
     const int lane = threadIdx.x & (kWave - 1);
-    const int x0 = xs + lane * kPxPerLane;
-    if (x0 >= g.W) return;
+    const int x0 = min(xs + lane * kPxPerLane, VEC ? g.W - kPxPerLane : g.W - 1);
     int c0; uint32_t rem0;
     axis_left(g.ax, x0, c0, rem0);
     const float Dm1 = static_cast<float>(D - 1);
     const int Dm2 = D - 2;
     const int RS = lut_row_stride(D);
     const int PS = lut_pair_stride(D);
+    const float RS4 = static_cast<float>(4 * RS), PS4 = static_cast<float>(4 * PS);
+    const float Dm2f = static_cast<float>(Dm2);
+    (void)PS;
     float out[3][4];
     float r0[9], d01[9], d12[9];
     if (FASTMAP) {
@@ -221,23 +221,30 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
 #pragma unroll
             for (int l = 0; l < 9; ++l) S[l] = fmaf(du, s1[l] - s0[l], s0[l]);
         }
-        int ir, ig, ib; float dr, dg, db;
-        decode(px[0][k], Dm1, Dm2, ir, dr);
-        decode(px[1][k], Dm1, Dm2, ig, dg);
-        decode(px[2][k], Dm1, Dm2, ib, db);
+        // decode in float: f = min(floor(q), D-2), d = q - f; LDS byte offsets by float FMA
+        // (exact: every value stays below 2^24)
+        float fv[3], dd[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            const float q = fminf(fmaxf(px[c][k], 0.f), 1.f) * Dm1;
+            fv[c] = fminf(floorf(q), Dm2f);
+            dd[c] = q - fv[c];
+        }
+        const float dr = dd[0], dg = dd[1], db = dd[2];
+        const float ob[3] = {fv[1] * 12.f, fmaf(fv[2], 12.f, PS4), fmaf(fv[2], 12.f, 2.f * PS4)};
         float acc[3] = {bias3[0], bias3[1], bias3[2]};
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
-            const int ia = (p == 2) ? ig : ir;
+            const float fa = (p == 2) ? fv[1] : fv[0];
             const float da = (p == 2) ? dg : dr;
-            const int ib2 = (p == 0) ? ig : ib;
             const float db2 = (p == 0) ? dg : db;
+            const uint32_t boff = static_cast<uint32_t>(fmaf(fa, RS4, ob[p]));
             // bilinear weights: w11 = a b, w10 = a (1-b), w01 = (1-a) b, w00 = (1-a)(1-b)
             const float w11 = da * db2;
             const float w10 = da - w11;
             const float w01 = db2 - w11;
             const float w00 = (1.f - da) - w01;
-            const float* t0 = Tl + (p * PS + __umul24(ia, RS) + __umul24(ib2, 3));
+            const float* t0 = reinterpret_cast<const float*>(reinterpret_cast<const char*>(Tl) + boff);
             const float* t1 = t0 + RS;
 #pragma unroll
             for (int c = 0; c < 3; ++c) {
@@ -258,10 +265,68 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
     store_px4<IO, VEC>(yout + 2 * plane, x0, g.W, out[2]);
 }
 
-// Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave runs.  Inside an
-// image sub-range the tiles are walked column-major (same segment, consecutive rows), so a
-// wave keeps its staged raw map rows for about h/H of a map cell's height in pixel rows and
-// only re-reads the map from memory when the segment or the pair of map rows changes.
+// One image's share [ta, tb) (local row-major tile indices) of a workgroup's chunk.  Inside
+// it the tiles are walked column-major (same segment, consecutive rows) in one contiguous
+// run per wave, so a wave keeps its staged raw map rows for about h/H of a map cell's
+// height in pixel rows and only re-reads the map when the segment or the pair of map rows
+// changes.  VEC is uniform per image, so the hot loop has a single load/store form.
+template <typename IO, typename MT, bool FASTMAP, bool VEC>
+__device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, int b, int ta, int tb,
+                                          int wave, int nw, float* Tl, float* aux, float* stage,
+                                          float* raw) {
+    const int D = a.D;
+    const int ya = ta / g.nseg;
+    const int nr = (tb - 1) / g.nseg - ya + 1;
+    const int total = nr * g.nseg;
+    const int q = (total + nw - 1) / nw;
+    const int k0 = min(total, wave * q);
+    const int k1 = min(total, k0 + q);
+    // first valid tile of the run
+    int seg = k0 / nr, yr = k0 - seg * nr, k = k0;
+    auto valid = [&](int sg, int r) {
+        const int lt = (ya + r) * g.nseg + sg;
+        return lt >= ta && lt < tb;
+    };
+    auto advance = [&](int& sg, int& r, int& kk) {   // to the next valid tile (or kk == k1)
+        do {
+            ++kk;
+            if (++r == nr) { r = 0; ++sg; }
+        } while (kk < k1 && !valid(sg, r));
+    };
+    if (k < k1 && !valid(seg, yr)) advance(seg, yr, k);
+    const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
+    stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R, min(a.R, 8));
+    float bias3[3] = {0.f, 0.f, 0.f};
+    if (a.bias) {
+        bias3[0] = a.bias[3 * b]; bias3[1] = a.bias[3 * b + 1]; bias3[2] = a.bias[3 * b + 2];
+    }
+    // Each tile loads its pixels, stages/blends the map and computes: with 16 waves per CU
+    // the other waves cover a wave's load latency (a prefetch of the next tile measured no
+    // faster and costs registers).
+    int st_seg = -1, st_iv = -1, clo = 0, ncols = 0;
+    while (k < k1) {
+        const int y = ya + yr;
+        const int xs = seg * kSeg;
+        float px[3][4];
+        load_tile<IO, VEC>(a, g, y, xs, px);
+        int iv; uint32_t remv;
+        axis_left(g.ay, y, iv, remv);
+        if (seg != st_seg || iv != st_iv) {
+            seg_columns(g, xs, clo, ncols);
+            stage_raw<MT>(a, g, iv, clo, ncols, raw);
+            st_seg = seg;
+            st_iv = iv;
+            wave_sync();
+        }
+        blend_rows(raw, stage, ncols, static_cast<float>(remv) * g.ay.inv);
+        wave_sync();
+        compute_tile<IO, FASTMAP, VEC>(a, g, Tl, stage, clo, D, y, xs, px, bias3);
+        wave_sync();   // the stage region is rewritten for the next tile
+        advance(seg, yr, k);
+    }
+}
+
+// Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave runs.
 template <typename IO, typename MT, bool FASTMAP>
 __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
     extern __shared__ float smem[];
@@ -269,7 +334,9 @@ __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
     float* Tl = smem;
     float* aux = smem + lut_floats(D);
     const int nw = blockDim.x / kWave;
-    const int wave = threadIdx.x / kWave;
+    // wave index as a scalar: everything derived from it (tile runs, rows, segments) stays
+    // wave-uniform, so the tile bookkeeping runs on the scalar unit with uniform branches
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     float* stage = aux + wave * a.ncol_max * (kMapStride + kRawStride);
     float* raw = stage + a.ncol_max * kMapStride;
 
@@ -278,76 +345,17 @@ __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
     const int64_t per = (a.total_tiles + G - 1) / G;
     int64_t t0 = static_cast<int64_t>(lb) * per;
     const int64_t t1 = min(a.total_tiles, t0 + per);
-    const int kc = min(a.R, 8);
     while (t0 < t1) {
         const int b = image_of_tile(a, t0);
         const Geo g = image_geo(a, b, sizeof(IO));
         const int64_t img_end = g.tile0 + static_cast<int64_t>(g.H) * g.nseg;
         const int64_t te = min(t1, img_end);
-        // local row-major tile range [ta, tb) of this image, walked column-major over its rows
         const int ta = static_cast<int>(t0 - g.tile0);
         const int tb = static_cast<int>(te - g.tile0);
-        const int ya = ta / g.nseg;
-        const int nr = (tb - 1) / g.nseg - ya + 1;
-        const int total = nr * g.nseg;
-        const int q = (total + nw - 1) / nw;
-        const int k0 = min(total, wave * q);
-        const int k1 = min(total, k0 + q);
-        // first valid tile of the run
-        int seg = k0 / nr, yr = k0 - seg * nr, k = k0;
-        auto valid = [&](int sg, int r) {
-            const int lt = (ya + r) * g.nseg + sg;
-            return lt >= ta && lt < tb;
-        };
-        auto advance = [&](int& sg, int& r, int& kk) {   // to the next valid tile (or kk == k1)
-            do {
-                ++kk;
-                if (++r == nr) { r = 0; ++sg; }
-            } while (kk < k1 && !valid(sg, r));
-        };
-        if (k < k1 && !valid(seg, yr)) advance(seg, yr, k);
-        float px[3][4];
-        if (k < k1) load_tile<IO>(a, g, ya + yr, seg * kSeg, px);   // in flight during the LUT rebuild
-        const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
-        stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R, kc);
-        float bias3[3] = {0.f, 0.f, 0.f};
-        if (a.bias) {
-            bias3[0] = a.bias[3 * b]; bias3[1] = a.bias[3 * b + 1]; bias3[2] = a.bias[3 * b + 2];
-        }
-        int st_seg = -1, st_iv = -1, clo = 0, ncols = 0;
-        // One tile: stage/blend the map, prefetch the next tile's pixels into `nxt`, compute
-        // the current tile from `cur`.  Two calls per iteration alternate the register sets,
-        // so the prefetched pixels are never copied.
-        auto do_tile = [&](float (&cur)[3][4], float (&nxt)[3][4]) {
-            const int y = ya + yr;
-            const int xs = seg * kSeg;
-            int iv; uint32_t remv;
-            axis_left(g.ay, y, iv, remv);
-            if (seg != st_seg || iv != st_iv) {
-                seg_columns(g, xs, clo, ncols);
-                stage_raw<MT>(a, g, iv, clo, ncols, raw);
-                st_seg = seg;
-                st_iv = iv;
-                wave_sync();
-            }
-            blend_rows(raw, stage, ncols, static_cast<float>(remv) * g.ay.inv);
-            int nseg2 = seg, nyr = yr, nk = k;
-            advance(nseg2, nyr, nk);
-            if (nk < k1) load_tile<IO>(a, g, ya + nyr, nseg2 * kSeg, nxt);
-            wave_sync();
-            if (g.vec_ok && xs + kSeg <= g.W)
-                compute_tile<IO, FASTMAP, true>(a, g, Tl, stage, clo, D, y, xs, cur, bias3);
-            else
-                compute_tile<IO, FASTMAP, false>(a, g, Tl, stage, clo, D, y, xs, cur, bias3);
-            wave_sync();   // the stage region is rewritten for the next tile
-            seg = nseg2; yr = nyr; k = nk;
-        };
-        float px2[3][4];
-        while (k < k1) {
-            do_tile(px, px2);
-            if (k >= k1) break;
-            do_tile(px2, px);
-        }
+        if (g.vec_ok)
+            run_image<IO, MT, FASTMAP, true>(a, g, b, ta, tb, wave, nw, Tl, aux, stage, raw);
+        else
+            run_image<IO, MT, FASTMAP, false>(a, g, b, ta, tb, wave, nw, Tl, aux, stage, raw);
         t0 = te;
         __syncthreads();   // every wave is done with Tl and aux before the next image
     }
