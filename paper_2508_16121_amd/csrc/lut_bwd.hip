@@ -207,12 +207,12 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
                 const float w10 = da - w11;
                 const float w01 = db - w11;
                 const float w00 = 1.f - da - db + w11;
-                const int slot = p * pairstep + ii[al] * rowstep + 3 * ii[be];
+                const int slot = p * pairstep + ii[al] * rowstep + kNode * ii[be];
                 const float* t0 = Tl + slot;
                 const float* t1 = t0 + rowstep;
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    const float T00 = t0[c], T01 = t0[3 + c], T10 = t1[c], T11 = t1[3 + c];
+                    const float T00 = t0[c], T01 = t0[kNode + c], T10 = t1[c], T11 = t1[kNode + c];
                     const float g = gy[c][k] * S[3 * c + p];
                     if (P.want_dT) {
                         int* q0 = dTl + slot;
@@ -220,8 +220,8 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
                         const float gs = g * sT;
                         lds_addi(q0 + c, fix(gs * w00));
                         lds_addi(q1 + c, fix(gs * w10));
-                        lds_addi(q0 + 3 + c, fix(gs * w01));
-                        lds_addi(q1 + 3 + c, fix(gs * w11));
+                        lds_addi(q0 + kNode + c, fix(gs * w01));
+                        lds_addi(q1 + kNode + c, fix(gs * w11));
                     }
                     gx[al] = fmaf(g, (1.f - db) * (T10 - T00) + db * (T11 - T01), gx[al]);
                     gx[be] = fmaf(g, (1.f - da) * (T01 - T00) + da * (T11 - T10), gx[be]);
@@ -402,7 +402,7 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
             for (int e = threadIdx.x; e < 9 * D * D; e += blockDim.x) {
                 const int l = e / (D * D), r = e - l * (D * D);
                 const int i = r / D, jj = r - i * D;
-                const float v = fabsf(Tl[(l % 3) * PS + i * RS + 3 * jj + l / 3]);
+                const float v = fabsf(Tl[(l % 3) * PS + i * RS + kNode * jj + l / 3]);
                 nf |= !(v <= FLT_MAX);
                 mT = fmaxf(mT, v);
             }

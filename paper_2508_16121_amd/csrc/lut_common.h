@@ -95,16 +95,18 @@ __device__ __forceinline__ void decode(float xv, float Dm1, int Dm2, int& i, flo
 // RS (the row stride) is 3*D padded to 10 or 22 (mod 32): the 3x3 neighbourhood of a cell
 // then maps to nine distinct LDS banks whether the LDS is viewed as 32 or 64 banks, which
 // matters because per-pixel noise scatters neighbouring pixels over adjacent cells.
+constexpr int kNode = 3;   // floats per LUT vertex (the three output channels)
+
 __host__ __device__ inline int lut_row_stride(int D) {
-    // 3D rounded up to the next value that is 10 or 22 modulo 32 (closed form, no loop)
-    const int rs = 3 * D, r = rs & 31;
+    // kNode*D rounded up to the next value that is 10 or 22 modulo 32 (closed form, no loop)
+    const int rs = kNode * D, r = rs & 31;
     return rs + (r <= 10 ? 10 - r : (r <= 22 ? 22 - r : 42 - r));
 }
 __host__ __device__ inline int lut_pair_stride(int D) { return D * lut_row_stride(D); }
 __host__ __device__ inline int lut_floats(int D) { return (3 * lut_pair_stride(D) + 3) & ~3; }
 
 __device__ __forceinline__ int lut_slot(int p, int i, int j, int c, int D) {
-    return p * lut_pair_stride(D) + i * lut_row_stride(D) + 3 * j + c;
+    return p * lut_pair_stride(D) + i * lut_row_stride(D) + kNode * j + c;
 }
 
 // Exact unsigned division num / d for num < 2^32 by a reciprocal multiply and at most two
@@ -168,7 +170,7 @@ __device__ inline void stage_luts(float* Tl, float* scratch, const float* U, con
             const int c = l / 3, p = l - 3 * c;
             const int i0 = hf ? half : 0;
             const int i1 = hf ? D : half;
-            float* out = Tl + p * PS + i0 * RS + 3 * j + c;
+            float* out = Tl + p * PS + i0 * RS + kNode * j + c;
             const float* urow = Us + (l * D + i0) * KC;
             for (int i = i0; i < i1; ++i, out += RS, urow += KC) {
                 const float4 ua = *reinterpret_cast<const float4*>(urow);

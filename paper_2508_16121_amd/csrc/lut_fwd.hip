@@ -231,7 +231,8 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
             dd[c] = q - fv[c];
         }
         const float dr = dd[0], dg = dd[1], db = dd[2];
-        const float ob[3] = {fv[1] * 12.f, fmaf(fv[2], 12.f, PS4), fmaf(fv[2], 12.f, 2.f * PS4)};
+        constexpr float NB = 4.f * kNode;   // bytes per vertex
+        const float ob[3] = {fv[1] * NB, fmaf(fv[2], NB, PS4), fmaf(fv[2], NB, 2.f * PS4)};
         float acc[3] = {bias3[0], bias3[1], bias3[2]};
 #pragma unroll
         for (int p = 0; p < 3; ++p) {
@@ -250,8 +251,8 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
             for (int c = 0; c < 3; ++c) {
                 float phi = w00 * t0[c];
                 phi = fmaf(w10, t1[c], phi);
-                phi = fmaf(w01, t0[3 + c], phi);
-                phi = fmaf(w11, t1[3 + c], phi);
+                phi = fmaf(w01, t0[kNode + c], phi);
+                phi = fmaf(w11, t1[kNode + c], phi);
                 acc[c] = fmaf(S[3 * c + p], phi, acc[c]);
             }
         }
