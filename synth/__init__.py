@@ -64,6 +64,26 @@ def spatial_map(g: np.random.Generator, n_img: int, h: int, w: int) -> np.ndarra
     return g.uniform(0.0, 1.0, size=(n_img, N_LUT, h, w)).astype(np.float32)
 
 
+def grids(g: np.random.Generator, n_img: int, K: int = 6, Ds: int = 17):
+    """Bilateral grids [n][K][3][Ds][Ds] ~ N(0, 0.1), plane weights [n][K][3] ~ U(0, 1) and
+    biases [n][K] ~ N(0, 0.01), float32, drawn in that order."""
+    gr = g.normal(0.0, 0.1, size=(n_img, K, 3, Ds, Ds)).astype(np.float32)
+    gw = g.uniform(0.0, 1.0, size=(n_img, K, 3)).astype(np.float32)
+    gb = g.normal(0.0, 0.01, size=(n_img, K)).astype(np.float32)
+    return gr, gw, gb
+
+
+def grid_case(seed: int, H: int, W: int, D: int, R: int, h: int, w: int, K: int = 6, Ds: int = 17):
+    """One image with factors, map and grids: X, U, s, V, map, grids, weights, biases from
+    default_rng(seed) in that order."""
+    g = rng(seed)
+    x = image(g, H, W)[None]
+    U, s, V = factors(g, 1, D, R)
+    m = spatial_map(g, 1, h, w)
+    gr, gw, gb = grids(g, 1, K, Ds)
+    return Case(x, U, s, V, m), gr, gw, gb
+
+
 def map_size(H: int, W: int, div: int = 8):
     """Map resolution at 1/div of the image: (ceil(H/div), ceil(W/div))."""
     return -(-H // div), -(-W // div)
