@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5")
+    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run device-to-device copies of one 4K fp32 frame (99.5 MB), the reference "
@@ -125,6 +125,27 @@ def cpu_baseline(case, budget_s):
         y0 += band
     return {"value": round(px / t_total / 1e6, 3), "unit": "Mpix/s", "cores": 1, "kind": "oracle",
             "sample": f"{rows} of {H} rows of the {W}x{H} frame (fp64 NumPy, one thread), {t_total:.1f} s"}
+
+
+def row_g1(svd, torch, synth, args):
+    """4K frame with the paper's fused slicing: K = 6 bilateral grids of 3 planes, 17x17."""
+    c, gr, gw, gb = synth.grid_case(43, 2160, 3840, 33, 8, 270, 480)
+    sets = []
+    for k in range(N_ROT):
+        sets.append([torch.from_numpy(a).cuda() for a in (c.x, c.U, c.s, c.V, c.smap, gr, gw, gb)]
+                    + [torch.empty_like(torch.from_numpy(c.x)).cuda()])
+    torch.cuda.synchronize()
+
+    def step(i):
+        b = sets[i % N_ROT]
+        svd.apply_grid(*b[:8], out=b[8])
+
+    ms, ms_kernel = launch_times(step, args.steps, args.warmup, torch)
+    npx = 2160 * 3840
+    bytes_alg = npx * 24 + 9 * 270 * 480 * 4 + 9 * 33 * 8 * 2 * 4 + 9 * 8 * 4 + gr.nbytes + gw.nbytes + gb.nbytes
+    return {"workload": "svdlut_apply_grid 1x3x2160x3840 fp32, D=33 R=8, map 9x270x480, K=6 grids x 3 planes 17x17",
+            "ms": round(ms, 5), "kernel_ms": round(ms_kernel, 5), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1),
+            "roofline": roof(bytes_alg, ms_kernel)}
 
 
 def row_c1(svd, torch, synth, args):
@@ -280,9 +301,9 @@ def main():
         ms_copy = event_time(lambda i: dst.copy_(src), max(5, args.steps // 4), 2, torch)
         out["copy_probe"] = {"bytes_per_copy": 2 * src.numel() * 4, "ms": round(ms_copy, 5),
                              "gb_s": round(2 * src.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
-    want = {"c1", "c3", "c4", "c5"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
+    want = {"c1", "c3", "c4", "c5", "g1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
     rows = {}
-    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5)):
+    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1)):
         if name in want:
             rows[name] = fn(svd, torch, synth, args)
             print(f"row {name} done", file=sys.stderr, flush=True)

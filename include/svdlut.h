@@ -84,6 +84,32 @@ svdlut_status svdlut_apply(const void* x, void* y, svdlut_dtype io,
                            int32_t D, int32_t R, hipStream_t stream);
 
 /*
+ * svdlut_apply_grid — svdlut_apply fused with 2D bilateral-grid slicing (supplementary Sec.
+ * "2D Slicing", Eqs. query_grid, lookup_grid, adjacent_grid, bilinear_grid and the weighted
+ * sum of the three planes; Sec. "Slicing and LUT Transform", Eq. slicing_transform):
+ *   Y_c = (svdlut_apply)_c + sum over grids k with k mod 3 = c of Psi^k,
+ *   Psi^k = w^k_xy psi_xy + w^k_xc psi_xc + w^k_yc psi_yc + b^k,
+ * where psi_ab is the bilinear lookup of plane ab of grid k at the query
+ *   xy: (x', y'),  xc: (x', p_c),  yc: (y', p_c),   c = k mod 3,
+ * with x' = x/(W-1), y' = y/(H-1) evaluated exactly as x*(Ds-1)/(W-1) (a size-1 image axis
+ * queries 0) and p_c decoded like the LUT colours with Ds vertices.
+ *   grids: [B][K][3][Ds][Ds] float32, planes in the order (xy, xc, yc), each indexed
+ *          [alpha][beta] = [x][y], [x][c], [y][c]
+ *   gw:    [B][K][3] float32 plane weights (w_xy, w_xc, w_yc);  gb: [B][K] float32 biases
+ *   K:     1..12 (the paper uses 6: two grids per channel);  Ds: 2..33 (the paper: 17)
+ * Other arguments as svdlut_apply.  The library folds the grids of one output channel into
+ * one weighted grid per workgroup (slicing is linear in the planes), so the result equals
+ * the definition up to float32 rounding.  Errors: as svdlut_apply, plus EINVAL for K or Ds
+ * out of range or a null grids/gw/gb.
+ */
+svdlut_status svdlut_apply_grid(const void* x, void* y, svdlut_dtype io, const float* U, const float* s,
+                                const float* V, const void* map, svdlut_dtype map_dt, const float* bias,
+                                const float* grids, const float* gw, const float* gb, int32_t K,
+                                int32_t Ds, int32_t B, int32_t H, int32_t W, int32_t h, int32_t w,
+                                int32_t D, int32_t R, hipStream_t stream);
+
+
+/*
  * svdlut_apply_bwd — gradients of a scalar loss through svdlut_apply, given
  * dy = dL/dY [B][3][H][W] (dtype io).  By the chain rule of the forward:
  *   dT_l[i_a + a][i_b + b] += dy_c * S_l * w_alpha(a) * w_beta(b)   (then dU, ds, dV below)

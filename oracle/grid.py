@@ -69,6 +69,28 @@ def slice_grids(x, g, gw, gb):
     return np.einsum("kp,kphw->khw", gw, psi) + gb[:, None, None]
 
 
+def slice_grids_at(x, g, gw, gb, ys, xs):
+    """The same Psi^k evaluated only at pixels (ys[n], xs[n]) of an image of size x.shape:
+    [K][len(ys)] (for sampled checks of large frames)."""
+    x = np.asarray(x)
+    g = np.asarray(g, dtype=np.float64)
+    gw = np.asarray(gw, dtype=np.float64)
+    gb = np.asarray(gb, dtype=np.float64)
+    K, _, Ds, _ = g.shape
+    _, H, W = x.shape
+    ys = np.asarray(ys)
+    xs = np.asarray(xs)
+    ix_all, dx_all = axis_coords(W, Ds)
+    iy_all, dy_all = axis_coords(H, Ds)
+    IX, DX, IY, DY = ix_all[xs], dx_all[xs], iy_all[ys], dy_all[ys]
+    out = np.zeros((K, ys.size))
+    for k in range(K):
+        ic, dc = decode(x[k % 3][ys, xs], Ds)
+        out[k] = (gw[k, 0] * bilinear(g[k, 0], IX, DX, IY, DY) + gw[k, 1] * bilinear(g[k, 1], IX, DX, ic, dc)
+                  + gw[k, 2] * bilinear(g[k, 2], IY, DY, ic, dc) + gb[k])
+    return out
+
+
 def transform_grid(x, T, smap, g, gw, gb, bias=None):
     """Fused slicing and LUT transform of one image (supp. Eq. slicing_transform).
 

@@ -29,6 +29,8 @@ SIGS = {
     "svdlut_version": (C.c_char_p, []),
     "svdlut_reconstruct": (I32, [P, P, P, P, I32, I32, I32, P]),
     "svdlut_apply": (I32, [P, P, I32, P, P, P, P, I32, P, I32, I32, I32, I32, I32, I32, I32, P]),
+    "svdlut_apply_grid": (I32, [P, P, I32, P, P, P, P, I32, P, P, P, P, I32, I32,
+                                I32, I32, I32, I32, I32, I32, I32, P]),
     "svdlut_apply_bwd_workspace_size": (SZ, [I32, I32]),
     "svdlut_apply_bwd": (I32, [P, P, I32, P, P, P, P, I32, P, P, P, P, P, P,
                                I32, I32, I32, I32, I32, I32, I32, P, SZ, P]),

@@ -78,16 +78,16 @@ static svdlut_status check_dtype(svdlut_dtype t, const char* what) {
 
 // Default launch shape of the fused apply: one 1024-thread workgroup per CU (16 waves, the
 // most the kernel's register budget allows) when its LDS fits, else the largest that fits.
-static int default_block(int D, int R, int ncol_max, const DeviceInfo& di) {
+static int default_block(int D, int R, int ncol_max, const DeviceInfo& di, int Ds = 0) {
     for (int b : {1024, 512, 256, 128, 64})
-        if (apply_lds_bytes(D, R, b, ncol_max) <= static_cast<size_t>(di.lds_per_block)) return b;
+        if (apply_lds_bytes(D, R, b, ncol_max, Ds) <= static_cast<size_t>(di.lds_per_block)) return b;
     return 0;
 }
 
 // Workgroups per CU that can be resident: the kernel holds up to 128 VGPRs per lane, so a CU
 // fits 16 of its waves (4 per SIMD); LDS may allow fewer.
-static int blocks_per_cu(int D, int R, int block, int ncol_max, const DeviceInfo& di) {
-    const size_t lds = apply_lds_bytes(D, R, block, ncol_max);
+static int blocks_per_cu(int D, int R, int block, int ncol_max, const DeviceInfo& di, int Ds = 0) {
+    const size_t lds = apply_lds_bytes(D, R, block, ncol_max, Ds);
     const int by_lds = static_cast<int>(di.lds_per_cu / std::max<size_t>(lds, 1));
     const int by_waves = 16 / std::max(block / kWave, 1);
     return std::max(1, std::min(by_lds, by_waves));
@@ -112,10 +112,12 @@ svdlut_status svdlut_reconstruct(const float* U, const float* s, const float* V,
     return launch_reconstruct(U, s, V, T, n_luts, D, R, stream);
 }
 
-svdlut_status svdlut_apply(const void* x, void* y, svdlut_dtype io, const float* U, const float* s,
-                           const float* V, const void* map, svdlut_dtype map_dt, const float* bias,
-                           int32_t B, int32_t H, int32_t W, int32_t h, int32_t w, int32_t D,
-                           int32_t R, hipStream_t stream) {
+// Shared by svdlut_apply and svdlut_apply_grid (K == 0: no grids).
+static svdlut_status apply_impl(const void* x, void* y, svdlut_dtype io, const float* U, const float* s,
+                                const float* V, const void* map, svdlut_dtype map_dt, const float* bias,
+                                const float* grids, const float* gw, const float* gb, int32_t K,
+                                int32_t Ds, int32_t B, int32_t H, int32_t W, int32_t h, int32_t w,
+                                int32_t D, int32_t R, hipStream_t stream) {
     if (!x || !y || !U || !s || !V || !map) return fail(SVDLUT_EINVAL, "apply: null pointer");
     SVDLUT_TRY(check_dtype(io, "apply io"));
     SVDLUT_TRY(check_dtype(map_dt, "apply map"));
@@ -131,13 +133,35 @@ svdlut_status svdlut_apply(const void* x, void* y, svdlut_dtype io, const float*
     a.total_tiles = static_cast<int64_t>(B) * H * ((W + kSeg - 1) / kSeg);
     a.ncol_max = map_cols_bound(W, w);
     a.fast_map = map_fast_ok(W, w) ? 1 : 0;
-    a.block = default_block(D, R, a.ncol_max, di);
+    a.grids = grids; a.gw = gw; a.gb = gb; a.K = K; a.Ds = Ds;
+    const int lds_ds = K > 0 ? Ds : 0;
+    a.block = default_block(D, R, a.ncol_max, di, lds_ds);
     if (a.block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply: map too wide for LDS staging");
-    const int64_t max_grid = static_cast<int64_t>(di.cus) * blocks_per_cu(D, R, a.block, a.ncol_max, di);
+    const int64_t max_grid = static_cast<int64_t>(di.cus) * blocks_per_cu(D, R, a.block, a.ncol_max, di, lds_ds);
     const int64_t tiles_per_block_min = a.block / kWave;   // at least one tile per wave
     a.grid = static_cast<int>(std::max<int64_t>(1, std::min(max_grid, (a.total_tiles + tiles_per_block_min - 1) / tiles_per_block_min)));
     a.io = io; a.map_dt = map_dt;
     return launch_apply(a, stream);
+}
+
+svdlut_status svdlut_apply(const void* x, void* y, svdlut_dtype io, const float* U, const float* s,
+                           const float* V, const void* map, svdlut_dtype map_dt, const float* bias,
+                           int32_t B, int32_t H, int32_t W, int32_t h, int32_t w, int32_t D,
+                           int32_t R, hipStream_t stream) {
+    return apply_impl(x, y, io, U, s, V, map, map_dt, bias, nullptr, nullptr, nullptr, 0, 0, B, H, W,
+                      h, w, D, R, stream);
+}
+
+svdlut_status svdlut_apply_grid(const void* x, void* y, svdlut_dtype io, const float* U, const float* s,
+                                const float* V, const void* map, svdlut_dtype map_dt, const float* bias,
+                                const float* grids, const float* gw, const float* gb, int32_t K,
+                                int32_t Ds, int32_t B, int32_t H, int32_t W, int32_t h, int32_t w,
+                                int32_t D, int32_t R, hipStream_t stream) {
+    if (!grids || !gw || !gb) return fail(SVDLUT_EINVAL, "apply_grid: null grid pointer");
+    if (K < 1 || K > kMaxGrids) return fail(SVDLUT_EINVAL, "apply_grid: K must be in [1, 12]");
+    if (Ds < 2 || Ds > kMaxDs) return fail(SVDLUT_EINVAL, "apply_grid: Ds must be in [2, 33]");
+    return apply_impl(x, y, io, U, s, V, map, map_dt, bias, grids, gw, gb, K, Ds, B, H, W, h, w, D, R,
+                      stream);
 }
 
 size_t svdlut_apply_bwd_workspace_size(int32_t B, int32_t D) {

@@ -59,9 +59,20 @@ struct ApplyLaunch {
     int32_t block;                 // threads per workgroup
     int32_t grid;                  // workgroups
     svdlut_dtype io, map_dt;
+    // optional 2D bilateral grids (K == 0: none): grids [B][K][3][Ds][Ds], gw [B][K][3], gb [B][K]
+    const float* grids;
+    const float* gw;
+    const float* gb;
+    int32_t K, Ds;
 };
 
-size_t apply_lds_bytes(int D, int R, int block, int ncol_max);
+constexpr int kMaxGrids = 12;
+constexpr int kMaxDs = 33;
+// LDS floats of the combined grid planes (one xy, xc and yc plane per output channel)
+__host__ __device__ inline int grid_plane_stride(int Ds) { return Ds | 1; }
+__host__ __device__ inline int grid_floats(int Ds) { return 9 * Ds * grid_plane_stride(Ds); }
+
+size_t apply_lds_bytes(int D, int R, int block, int ncol_max, int Ds = 0);
 int map_cols_bound(int W, int w);
 bool map_fast_ok(int W, int w);
 svdlut_status launch_apply(const ApplyLaunch& a, hipStream_t st);

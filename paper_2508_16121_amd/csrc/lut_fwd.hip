@@ -173,10 +173,21 @@ __device__ __forceinline__ void blend_rows(const float* raw, float* stage, int n
     }
 }
 
-template <typename IO, bool FASTMAP, bool VEC>
+// Grid slicing state of one tile: the combined planes in LDS, the spatial axis maps and the
+// tile row's grid coordinate along y.
+struct GridTile {
+    const float* Gl;     // [3 channels][3 planes (xy, xc, yc)][Ds][Dsp]
+    AxisMap gax;         // W -> Ds
+    int iy;
+    float dy;
+    int Ds, Dsp;
+};
+
+template <typename IO, bool FASTMAP, bool VEC, bool GRID>
 __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g, const float* Tl,
                                              const float* stage, int clo, int D, int y, int xs,
-                                             const float (&px)[3][4], const float (&bias3)[3]) {
+                                             const float (&px)[3][4], const float (&bias3)[3],
+                                             const GridTile& gt) {
     // Lanes past the row end work on the row's last pixels (the same x0 as load_tile) and
     // store the same values again, so every lane issues the same loads and stores.
     const int lane = threadIdx.x & (kWave - 1);
@@ -256,6 +267,46 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
                 acc[c] = fmaf(S[3 * c + p], phi, acc[c]);
             }
         }
+        if (GRID) {
+            // 2D slicing (supp. Eqs. query_grid to bilinear_grid): planes xy (x, y),
+            // xc (x, X_c) and yc (y, X_c) of the channel's combined grid
+            int ixg; uint32_t rxg;
+            axis_left(gt.gax, x0 + k, ixg, rxg);
+            const float dxg = static_cast<float>(rxg) * gt.gax.inv;
+            const int P = gt.Ds * gt.Dsp;
+            const float Dsm1 = static_cast<float>(gt.Ds - 1), Dsm2 = static_cast<float>(gt.Ds - 2);
+            const float wy1 = gt.dy, wx1 = dxg;
+            const float wxy11 = wx1 * wy1, wxy10 = wx1 - wxy11, wxy01 = wy1 - wxy11;
+            const float wxy00 = (1.f - wx1) - wxy01;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                const float q = fminf(fmaxf(px[c][k], 0.f), 1.f) * Dsm1;
+                const float fc = fminf(floorf(q), Dsm2);
+                const float dc = q - fc;
+                const int ic = static_cast<int>(fc);
+                const float* G0 = gt.Gl + 3 * c * P;
+                const float* txy = G0 + ixg * gt.Dsp + gt.iy;
+                const float* txc = G0 + P + ixg * gt.Dsp + ic;
+                const float* tyc = G0 + 2 * P + gt.iy * gt.Dsp + ic;
+                float v = wxy00 * txy[0];
+                v = fmaf(wxy10, txy[gt.Dsp], v);
+                v = fmaf(wxy01, txy[1], v);
+                v = fmaf(wxy11, txy[gt.Dsp + 1], v);
+                const float wc11x = wx1 * dc, wc10x = wx1 - wc11x, wc01x = dc - wc11x;
+                const float wc00x = (1.f - wx1) - wc01x;
+                v = fmaf(wc00x, txc[0], v);
+                v = fmaf(wc10x, txc[gt.Dsp], v);
+                v = fmaf(wc01x, txc[1], v);
+                v = fmaf(wc11x, txc[gt.Dsp + 1], v);
+                const float wc11y = wy1 * dc, wc10y = wy1 - wc11y, wc01y = dc - wc11y;
+                const float wc00y = (1.f - wy1) - wc01y;
+                v = fmaf(wc00y, tyc[0], v);
+                v = fmaf(wc10y, tyc[gt.Dsp], v);
+                v = fmaf(wc01y, tyc[1], v);
+                v = fmaf(wc11y, tyc[gt.Dsp + 1], v);
+                acc[c] += v;
+            }
+        }
 #pragma unroll
         for (int c = 0; c < 3; ++c) out[c][k] = acc[c];
     }
@@ -271,9 +322,9 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
 // run per wave, so a wave keeps its staged raw map rows for about h/H of a map cell's
 // height in pixel rows and only re-reads the map when the segment or the pair of map rows
 // changes.  VEC is uniform per image, so the hot loop has a single load/store form.
-template <typename IO, typename MT, bool FASTMAP, bool VEC>
+template <typename IO, typename MT, bool FASTMAP, bool VEC, bool GRID>
 __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, int b, int ta, int tb,
-                                          int wave, int nw, float* Tl, float* aux, float* stage,
+                                          int wave, int nw, float* Tl, float* Gl, float* aux, float* stage,
                                           float* raw) {
     const int D = a.D;
     const int ya = ta / g.nseg;
@@ -295,12 +346,40 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
         } while (kk < k1 && !valid(sg, r));
     };
     if (k < k1 && !valid(seg, yr)) advance(seg, yr, k);
+    GridTile gt{};
+    if (GRID) {
+        // Combined planes: slicing is linear in the planes, so the K grids of one output
+        // channel (k mod 3 = c) collapse into one grid whose plane is sum_k w^k_plane g^k_plane
+        // (the previous image's readers are done: the caller synchronised).
+        gt.Ds = a.Ds;
+        gt.Dsp = grid_plane_stride(a.Ds);
+        const int P = a.Ds * gt.Dsp;
+        const float* gsrc = a.grids + static_cast<size_t>(b) * a.K * 3 * a.Ds * a.Ds;
+        const float* wsrc = a.gw + static_cast<size_t>(b) * a.K * 3;
+        for (int e = threadIdx.x; e < 9 * a.Ds * a.Ds; e += blockDim.x) {
+            const int cp = e / (a.Ds * a.Ds);            // 3 * channel + plane
+            const int r = e - cp * (a.Ds * a.Ds);
+            const int i = r / a.Ds, j = r - i * a.Ds;
+            const int c = cp / 3, pl = cp - 3 * c;
+            float v = 0.f;
+            for (int kk = c; kk < a.K; kk += 3)
+                v = fmaf(wsrc[3 * kk + pl], gsrc[(static_cast<size_t>(kk) * 3 + pl) * a.Ds * a.Ds + r], v);
+            Gl[cp * P + i * gt.Dsp + j] = v;
+        }
+        gt.Gl = Gl;
+        gt.gax = make_axis(g.W, a.Ds);
+    }
     const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
     stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R, min(a.R, 8));
     float bias3[3] = {0.f, 0.f, 0.f};
     if (a.bias) {
         bias3[0] = a.bias[3 * b]; bias3[1] = a.bias[3 * b + 1]; bias3[2] = a.bias[3 * b + 2];
     }
+    if (GRID) {
+        const float* bsrc = a.gb + static_cast<size_t>(b) * a.K;
+        for (int kk = 0; kk < a.K; ++kk) bias3[kk % 3] += bsrc[kk];
+    }
+    const AxisMap gay = GRID ? make_axis(g.H, a.Ds) : AxisMap{};
     // Each tile loads its pixels, stages/blends the map and computes: with 16 waves per CU
     // the other waves cover a wave's load latency (a prefetch of the next tile measured no
     // faster and costs registers).
@@ -321,19 +400,25 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
         }
         blend_rows(raw, stage, ncols, static_cast<float>(remv) * g.ay.inv);
         wave_sync();
-        compute_tile<IO, FASTMAP, VEC>(a, g, Tl, stage, clo, D, y, xs, px, bias3);
+        if (GRID) {
+            uint32_t ry;
+            axis_left(gay, y, gt.iy, ry);
+            gt.dy = static_cast<float>(ry) * gay.inv;
+        }
+        compute_tile<IO, FASTMAP, VEC, GRID>(a, g, Tl, stage, clo, D, y, xs, px, bias3, gt);
         wave_sync();   // the stage region is rewritten for the next tile
         advance(seg, yr, k);
     }
 }
 
 // Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave runs.
-template <typename IO, typename MT, bool FASTMAP>
+template <typename IO, typename MT, bool FASTMAP, bool GRID>
 __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
     extern __shared__ float smem[];
     const int D = a.D;
     float* Tl = smem;
-    float* aux = smem + lut_floats(D);
+    float* Gl = smem + lut_floats(D);
+    float* aux = Gl + (GRID ? ((grid_floats(a.Ds) + 3) & ~3) : 0);
     const int nw = blockDim.x / kWave;
     // wave index as a scalar: everything derived from it (tile runs, rows, segments) stays
     // wave-uniform, so the tile bookkeeping runs on the scalar unit with uniform branches
@@ -354,9 +439,9 @@ __global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
         const int ta = static_cast<int>(t0 - g.tile0);
         const int tb = static_cast<int>(te - g.tile0);
         if (g.vec_ok)
-            run_image<IO, MT, FASTMAP, true>(a, g, b, ta, tb, wave, nw, Tl, aux, stage, raw);
+            run_image<IO, MT, FASTMAP, true, GRID>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
         else
-            run_image<IO, MT, FASTMAP, false>(a, g, b, ta, tb, wave, nw, Tl, aux, stage, raw);
+            run_image<IO, MT, FASTMAP, false, GRID>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
         t0 = te;
         __syncthreads();   // every wave is done with Tl and aux before the next image
     }
@@ -374,24 +459,32 @@ bool map_fast_ok(int W, int w) {
     return static_cast<int64_t>(3) * (w - 1) <= static_cast<int64_t>(W - 1);
 }
 
-size_t apply_lds_bytes(int D, int R, int block, int ncol_max) {
+size_t apply_lds_bytes(int D, int R, int block, int ncol_max, int Ds) {
     const size_t lut = static_cast<size_t>(lut_floats(D));
     (void)R;
+    const size_t grid = Ds > 0 ? static_cast<size_t>((grid_floats(Ds) + 3) & ~3) : 0;
     const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
     const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * (kMapStride + kRawStride);
-    return sizeof(float) * (lut + std::max(scratch, stage));
+    return sizeof(float) * (lut + grid + std::max(scratch, stage));
 }
 
 template <typename IO, typename MT>
 static void launch_typed(const ApplyLaunch& a, size_t lds, hipStream_t st) {
-    if (a.fast_map)
-        hipLaunchKernelGGL((apply_kernel<IO, MT, true>), dim3(a.grid), dim3(a.block), lds, st, a);
-    else
-        hipLaunchKernelGGL((apply_kernel<IO, MT, false>), dim3(a.grid), dim3(a.block), lds, st, a);
+    if (a.K > 0) {
+        if (a.fast_map)
+            hipLaunchKernelGGL((apply_kernel<IO, MT, true, true>), dim3(a.grid), dim3(a.block), lds, st, a);
+        else
+            hipLaunchKernelGGL((apply_kernel<IO, MT, false, true>), dim3(a.grid), dim3(a.block), lds, st, a);
+    } else {
+        if (a.fast_map)
+            hipLaunchKernelGGL((apply_kernel<IO, MT, true, false>), dim3(a.grid), dim3(a.block), lds, st, a);
+        else
+            hipLaunchKernelGGL((apply_kernel<IO, MT, false, false>), dim3(a.grid), dim3(a.block), lds, st, a);
+    }
 }
 
 svdlut_status launch_apply(const ApplyLaunch& a, hipStream_t st) {
-    const size_t lds = apply_lds_bytes(a.D, a.R, a.block, a.ncol_max);
+    const size_t lds = apply_lds_bytes(a.D, a.R, a.block, a.ncol_max, a.K > 0 ? a.Ds : 0);
     if (a.io == SVDLUT_F32) {
         if (a.map_dt == SVDLUT_F32) launch_typed<float, float>(a, lds, st);
         else launch_typed<float, __half>(a, lds, st);

@@ -85,6 +85,40 @@ def apply(x, U, s, V, smap, bias=None, out=None):
     return out
 
 
+
+def apply_grid(x, U, s, V, smap, grids, gw, gb, bias=None, out=None):
+    """svdlut_apply fused with 2D bilateral-grid slicing (svdlut_apply_grid).
+
+    grids [B][K][3][Ds][Ds] (planes xy, xc, yc), gw [B][K][3], gb [B][K], all float32.
+    """
+    _need(x, "x", (torch.float32, torch.float16), 4)
+    B, C3, H, W = x.shape
+    if C3 != 3:
+        raise ValueError("x must be [B][3][H][W]")
+    D, R = _factors(U, s, V, B)
+    _need(smap, "smap", (torch.float32, torch.float16), 4)
+    if smap.shape[0] != B or smap.shape[1] != 9:
+        raise ValueError("smap must be [B][9][h][w]")
+    h, w = smap.shape[2], smap.shape[3]
+    _need(grids, "grids", ndim=5)
+    _need(gw, "gw", ndim=3)
+    _need(gb, "gb", ndim=2)
+    K, Ds = grids.shape[1], grids.shape[3]
+    if grids.shape != (B, K, 3, Ds, Ds) or gw.shape != (B, K, 3) or gb.shape != (B, K):
+        raise ValueError("grids must be [B][K][3][Ds][Ds], gw [B][K][3], gb [B][K]")
+    if bias is not None:
+        _need(bias, "bias")
+        if bias.shape != (B, 3):
+            raise ValueError("bias must be [B][3]")
+    if out is None:
+        out = torch.empty_like(x)
+    _need(out, "out", (x.dtype,), 4)
+    lib = _lib.load()
+    check(lib.svdlut_apply_grid(_ptr(x), _ptr(out), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap),
+                                _DT[smap.dtype], _ptr(bias), _ptr(grids), _ptr(gw), _ptr(gb), K, Ds,
+                                B, H, W, h, w, D, R, _stream()), "svdlut_apply_grid")
+    return out
+
 def bwd_workspace(B, D, device):
     n = _lib.load().svdlut_apply_bwd_workspace_size(B, D)
     return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)

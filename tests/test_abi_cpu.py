@@ -67,6 +67,15 @@ def test_validation_happens_before_any_hip_call(lib):
     bad = [fake, fake, 7, fake, fake, fake, fake, 0, null]
     assert lib.svdlut_apply(*bad, 1, 4, 4, 1, 1, 33, 8, null) == 2
     assert "dtype" in _err(lib)
+    # grids: null grid pointers, K and Ds out of range (then the usual apply checks)
+    gargs = [fake, fake, 0, fake, fake, fake, fake, 0, null]
+    assert lib.svdlut_apply_grid(*gargs, null, fake, fake, 6, 17, 1, 4, 4, 1, 1, 33, 8, null) == 1
+    assert "grid" in _err(lib)
+    assert lib.svdlut_apply_grid(*gargs, fake, fake, fake, 0, 17, 1, 4, 4, 1, 1, 33, 8, null) == 1
+    assert lib.svdlut_apply_grid(*gargs, fake, fake, fake, 13, 17, 1, 4, 4, 1, 1, 33, 8, null) == 1
+    assert lib.svdlut_apply_grid(*gargs, fake, fake, fake, 6, 1, 1, 4, 4, 1, 1, 33, 8, null) == 1
+    assert lib.svdlut_apply_grid(*gargs, fake, fake, fake, 6, 34, 1, 4, 4, 1, 1, 33, 8, null) == 1
+    assert lib.svdlut_apply_grid(*gargs, fake, fake, fake, 6, 17, 0, 4, 4, 1, 1, 33, 8, null) == 1
     # backward: partial factor trio, missing or short workspace
     b = [fake, fake, 0, fake, fake, fake, fake, 0]
     assert lib.svdlut_apply_bwd(*b, fake, fake, null, fake, null, null, 1, 8, 8, 1, 1, 33, 8, fake, 1 << 30, null) == 1

@@ -1,0 +1,97 @@
+"""GPU parity of the apply kernel fused with 2D bilateral-grid slicing (svdlut_apply_grid)
+against the fp64 CPU oracle (oracle/grid.py), through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import grid as og
+from oracle import lut as ol
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+TOL16 = 2e-3
+
+
+@pytest.fixture(scope="module")
+def svd():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_2508_16121_amd as m
+    return m
+
+
+def dev(a, dtype=None):
+    t = torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    return t.to(dtype) if dtype is not None else t
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def _check(svd, x, U, s, V, m, gr, gw, gb, bias=None, io=torch.float32, mt=torch.float32, tol=TOL32, label=""):
+    say(f"apply_grid {label} x{tuple(x.shape)} grids{tuple(gr.shape)} io={io}")
+    xd, md = dev(x, io), dev(m, mt)
+    y = svd.apply_grid(xd, dev(U), dev(s), dev(V), md, dev(gr), dev(gw), dev(gb),
+                       None if bias is None else dev(bias))
+    ref = og.apply_grid(host(xd), U, s, V, host(md), gr, gw, gb, bias)
+    err = np.abs(host(y) - ref).max()
+    assert err <= tol, f"max-abs {err}"
+
+
+@pytest.mark.parametrize("shape", [
+    # B, H, W, D, R, h, w, K, Ds
+    (1, 64, 96, 17, 4, 8, 12, 6, 17),
+    (2, 37, 131, 33, 8, 5, 17, 6, 17),     # ragged rows, width not a multiple of 4
+    (1, 9, 513, 33, 8, 4, 65, 3, 5),      # three segments, last one pixel wide
+    (1, 1, 300, 5, 2, 1, 38, 6, 2),       # one row, Ds = 2
+    (1, 130, 1, 5, 2, 17, 1, 12, 33),     # one column, K = 12, Ds = 33
+    (3, 20, 20, 9, 3, 15, 15, 6, 9),      # per-pixel map path, batch of three
+])
+def test_apply_grid_parity(svd, shape):
+    B, H, W, D, R, h, w, K, Ds = shape
+    g = np.random.default_rng(sum(shape))
+    x = g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)
+    x.flat[::5] = (g.integers(0, Ds, x.size)[::5] / (Ds - 1)).astype(np.float32)   # exact grid knots
+    U, s, V = synth.factors(g, B, D, R)
+    m = synth.spatial_map(g, B, h, w)
+    gr, gw, gb = synth.grids(g, B, K, Ds)
+    bias = g.normal(0, 0.1, (B, 3)).astype(np.float32)
+    _check(svd, x, U, s, V, m, gr, gw, gb, bias, label=str(shape))
+
+
+def test_apply_grid_fp16_storage(svd):
+    c, gr, gw, gb = synth.grid_case(41, 108, 189, 33, 8, 14, 24)
+    _check(svd, c.x, c.U, c.s, c.V, c.smap, gr, gw, gb, io=torch.float16, mt=torch.float16, tol=TOL16,
+           label="fp16")
+
+
+def test_zero_grids_equal_plain_apply(svd):
+    c, gr, gw, gb = synth.grid_case(42, 64, 256, 33, 8, 8, 32)
+    args = [dev(a) for a in (c.x, c.U, c.s, c.V, c.smap)]
+    y0 = host(svd.apply(*args))
+    y1 = host(svd.apply_grid(*args, dev(gr), dev(np.zeros_like(gw)), dev(np.zeros_like(gb))))
+    assert np.array_equal(y0, y1)
+
+
+def test_apply_grid_4k_sampled(svd):
+    """3840x2160 fp32, D=33 R=8, 270x480 map, K=6 grids of 17x17: sampled pixels vs the oracle."""
+    c, gr, gw, gb = synth.grid_case(43, 2160, 3840, 33, 8, 270, 480)
+    say("apply_grid 4K frame")
+    y = host(svd.apply_grid(dev(c.x), dev(c.U), dev(c.s), dev(c.V), dev(c.smap), dev(gr), dev(gw), dev(gb)))[0]
+    T = ol.reconstruct(c.U, c.s, c.V)[0]
+    g = np.random.default_rng(44)
+    ys = np.concatenate([g.integers(0, 2160, 3000), [0, 2159, 0, 2159]])
+    xs = np.concatenate([g.integers(0, 3840, 3000), [0, 0, 3839, 3839]])
+    ref = ol.transform_at(c.x[0], T, c.smap[0], ys, xs)
+    Psi = og.slice_grids_at(c.x[0], gr[0], gw[0], gb[0], ys, xs)
+    for k in range(Psi.shape[0]):
+        ref[k % 3] += Psi[k]
+    assert np.abs(y[:, ys, xs] - ref).max() <= TOL32
+    assert np.isfinite(y).all()

@@ -184,3 +184,12 @@ def test_input_gradient_finite_differences():
         assert abs(fd - r["dx"][c, yy, xx]) <= 1e-3 * abs(fd) + 1e-6
         checked += 1
     assert checked > 40
+
+
+def test_sampled_slicing_matches_full():
+    x, gr, gw, gb = _case(seed=31, H=11, W=17)
+    Psi = og.slice_grids(x, gr, gw, gb)
+    g = np.random.default_rng(32)
+    ys = g.integers(0, 11, 50)
+    xs = g.integers(0, 17, 50)
+    np.testing.assert_allclose(og.slice_grids_at(x, gr, gw, gb, ys, xs), Psi[:, ys, xs], atol=0)
