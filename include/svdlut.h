@@ -123,8 +123,9 @@ svdlut_status svdlut_apply_grid(const void* x, void* y, svdlut_dtype io, const f
  *   float32; dbias [B][3] float32.
  * ws: device workspace of at least svdlut_apply_bwd_workspace_size(B, D) bytes, 256-byte
  *   aligned, owned by the caller; contents on entry are ignored.
- * Float atomics make dU, ds, dV, dmap and dbias depend on summation order at the level
- * of float32 rounding; dx is deterministic.
+ * dT is accumulated in fixed point per workgroup and summed in a fixed order, so dU, ds
+ * and dV are reproducible, as is dx; dmap and dbias are summed across workgroups with
+ * float atomics and depend on their order at the level of float32 rounding.
  */
 size_t svdlut_apply_bwd_workspace_size(int32_t B, int32_t D);
 svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io,
@@ -135,6 +136,33 @@ svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io,
                                int32_t B, int32_t H, int32_t W, int32_t h, int32_t w,
                                int32_t D, int32_t R, void* ws, size_t ws_bytes,
                                hipStream_t stream);
+
+/*
+ * svdlut_apply_grid_bwd — gradients of a scalar loss through svdlut_apply_grid, given
+ * dy = dL/dY.  The LUT and map part is svdlut_apply_bwd (same outputs, same rules); the
+ * grid part adds, by the chain rule of the slicing (supp. Sec. "2D Slicing"), per grid k of
+ * output channel c = k mod 3:
+ *   dgrids[k][plane][a][b] = w^k_plane * sum over pixels of dy_c * w_alpha * w_beta at the
+ *                            vertex (a, b) of the plane's query,
+ *   dgw[k][plane]          = sum over pixels of dy_c * psi^k_plane,
+ *   dgb[k]                 = sum over pixels of dy_c,
+ *   dx_c                  += dy_c * (Ds-1) * (d psi_xc/d p + d psi_yc/d p) of the weighted
+ *                            grids of channel c, inside [0, 1] (the spatial plane has none).
+ *   dgrids [B][K][3][Ds][Ds], dgw [B][K][3], dgb [B][K] float32: all set or all NULL.
+ * ws: at least svdlut_apply_grid_bwd_workspace_size(B, D, Ds) bytes (caller-owned, 256-byte
+ *   aligned) whenever dU or dgrids is requested.  The grid gradients are accumulated in
+ *   fixed point per workgroup and summed in a fixed order, so they are reproducible.
+ * Errors: as svdlut_apply_bwd, plus EINVAL for K, Ds out of range, a null grids/gw, a
+ * partial (dgrids, dgw, dgb) trio or a short workspace.
+ */
+size_t svdlut_apply_grid_bwd_workspace_size(int32_t B, int32_t D, int32_t Ds);
+svdlut_status svdlut_apply_grid_bwd(const void* x, const void* dy, svdlut_dtype io, const float* U,
+                                    const float* s, const float* V, const void* map, svdlut_dtype map_dt,
+                                    const float* grids, const float* gw, int32_t K, int32_t Ds, void* dx,
+                                    float* dU, float* ds, float* dV, float* dmap, float* dbias,
+                                    float* dgrids, float* dgw, float* dgb, int32_t B, int32_t H, int32_t W,
+                                    int32_t h, int32_t w, int32_t D, int32_t R, void* ws, size_t ws_bytes,
+                                    hipStream_t stream);
 
 /*
  * Batches of images of uneven size.  Image b of a batch lives in packed planar buffers at

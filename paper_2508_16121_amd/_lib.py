@@ -32,6 +32,9 @@ SIGS = {
     "svdlut_apply_grid": (I32, [P, P, I32, P, P, P, P, I32, P, P, P, P, I32, I32,
                                 I32, I32, I32, I32, I32, I32, I32, P]),
     "svdlut_apply_bwd_workspace_size": (SZ, [I32, I32]),
+    "svdlut_apply_grid_bwd_workspace_size": (SZ, [I32, I32, I32]),
+    "svdlut_apply_grid_bwd": (I32, [P, P, I32, P, P, P, P, I32, P, P, I32, I32, P, P, P, P, P, P, P, P, P,
+                                    I32, I32, I32, I32, I32, I32, I32, P, SZ, P]),
     "svdlut_apply_bwd": (I32, [P, P, I32, P, P, P, P, I32, P, P, P, P, P, P,
                                I32, I32, I32, I32, I32, I32, I32, P, SZ, P]),
     "svdlut_plan_create": (I32, [P, I32, I32, I32, I32, I32, P]),

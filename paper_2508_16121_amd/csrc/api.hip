@@ -164,6 +164,39 @@ svdlut_status svdlut_apply_grid(const void* x, void* y, svdlut_dtype io, const f
                       stream);
 }
 
+size_t svdlut_apply_grid_bwd_workspace_size(int32_t B, int32_t D, int32_t Ds) {
+    if (B < 1 || D < 2 || D > kMaxD || Ds < 2 || Ds > kMaxDs) return 0;
+    return ((bwd_workspace_bytes(B, D) + 255) & ~static_cast<size_t>(255)) + grid_bwd_workspace_bytes(B, Ds);
+}
+
+svdlut_status svdlut_apply_grid_bwd(const void* x, const void* dy, svdlut_dtype io, const float* U,
+                                    const float* s, const float* V, const void* map, svdlut_dtype map_dt,
+                                    const float* grids, const float* gw, int32_t K, int32_t Ds, void* dx,
+                                    float* dU, float* ds, float* dV, float* dmap, float* dbias,
+                                    float* dgrids, float* dgw, float* dgb, int32_t B, int32_t H, int32_t W,
+                                    int32_t h, int32_t w, int32_t D, int32_t R, void* ws, size_t ws_bytes,
+                                    hipStream_t stream) {
+    if (!grids || !gw) return fail(SVDLUT_EINVAL, "apply_grid_bwd: null grid pointer");
+    if (K < 1 || K > kMaxGrids) return fail(SVDLUT_EINVAL, "apply_grid_bwd: K must be in [1, 12]");
+    if (Ds < 2 || Ds > kMaxDs) return fail(SVDLUT_EINVAL, "apply_grid_bwd: Ds must be in [2, 33]");
+    const int ng = (dgrids != nullptr) + (dgw != nullptr) + (dgb != nullptr);
+    if (ng != 0 && ng != 3) return fail(SVDLUT_EINVAL, "apply_grid_bwd: dgrids, dgw, dgb must be all set or all NULL");
+    if (B < 1 || !dims_ok(H) || !dims_ok(W)) return fail(SVDLUT_EINVAL, "apply_grid_bwd: bad B, H or W");
+    SVDLUT_TRY(check_lut_dims(D, R));
+    const size_t lut_ws = (bwd_workspace_bytes(B, D) + 255) & ~static_cast<size_t>(255);
+    if ((ng == 3 || dU) && (!ws || ws_bytes < lut_ws + grid_bwd_workspace_bytes(B, Ds)))
+        return fail(SVDLUT_EINVAL, "apply_grid_bwd: workspace smaller than svdlut_apply_grid_bwd_workspace_size()");
+    // the LUT part writes dx (and the LUT gradients); the grid part then adds into dx
+    SVDLUT_TRY(svdlut_apply_bwd(x, dy, io, U, s, V, map, map_dt, dx, dU, ds, dV, dmap, dbias, B, H, W, h,
+                                w, D, R, ws, ws_bytes, stream));
+    GridBwdLaunch g{};
+    g.x = x; g.dy = dy; g.dx = dx; g.grids = grids; g.gw = gw;
+    g.part = ws ? reinterpret_cast<float*>(static_cast<char*>(ws) + lut_ws) : nullptr;
+    g.dgrids = dgrids; g.dgw = dgw; g.dgb = dgb;
+    g.B = B; g.H = H; g.W = W; g.K = K; g.Ds = Ds; g.io = io;
+    return launch_grid_bwd(g, stream);
+}
+
 size_t svdlut_apply_bwd_workspace_size(int32_t B, int32_t D) {
     if (B < 1 || D < 2 || D > kMaxD) return 0;
     return bwd_workspace_bytes(B, D);

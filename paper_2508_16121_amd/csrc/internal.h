@@ -97,6 +97,25 @@ struct BwdLaunch {
     svdlut_dtype io, map_dt;
 };
 svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st);
+int bwd_groups_per_image(int B);
+size_t bwd_workspace_bytes(int B, int D);
+
+// Backward of the bilateral-grid slicing; dx (if set) is accumulated into.
+struct GridBwdLaunch {
+    const void* x;
+    const void* dy;
+    void* dx;
+    const float* grids;
+    const float* gw;
+    float* part;                   // workspace, grid_bwd_workspace_bytes(B, Ds)
+    float* dgrids;                 // [B][K][3][Ds][Ds]; with dgw [B][K][3], dgb [B][K] (all or none)
+    float* dgw;
+    float* dgb;
+    int32_t B, H, W, K, Ds;
+    svdlut_dtype io;
+};
+size_t grid_bwd_workspace_bytes(int B, int Ds);
+svdlut_status launch_grid_bwd(const GridBwdLaunch& a, hipStream_t st);
 
 // ---------------------------------------------------------------- generator
 svdlut_status launch_loss(const void* y, const void* t, svdlut_dtype io, int64_t n, int kind,

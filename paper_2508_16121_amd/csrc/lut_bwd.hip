@@ -20,7 +20,7 @@
 // that one rounding.  Integer sums are also independent of the order of the atomics.
 // Non-finite dy, map or T values (or bounds beyond the float range) make the workgroup
 // report NaN for its dT and dmap contributions.
-#include "lut_common.h"
+#include "bwd_common.h"
 
 #include <algorithm>
 #include <cfloat>
@@ -40,27 +40,6 @@ struct BwdDev {
     int fast_map;
     int want_dT, want_dmap, want_dx, want_db;
 };
-
-__device__ __forceinline__ void lds_addi(int* p, int v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-__device__ __forceinline__ void gbl_add(float* p, float v) {
-    __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ int fix(float v) { return __float2int_rn(v); }
-
-// Largest power of two 2^e with n * m1 * m2 * 2^e < 2^30 (1 when a factor is 0); sets
-// `bad` when the bound does not fit the float exponent range.
-__device__ inline float fix_scale(float n, float m1, float m2, bool& bad) {
-    if (!(n > 0.f) || !(m1 > 0.f) || !(m2 > 0.f)) return 1.f;
-    int en, e1, e2;
-    frexpf(n, &en);
-    frexpf(m1, &e1);
-    frexpf(m2, &e2);
-    const int e = 30 - (en + e1 + e2);   // each factor f < 2^ef
-    if (e < -126) { bad = true; return 1.f; }
-    return ldexpf(1.f, min(e, 126));
-}
 
 // Geometry shared by all tiles of a workgroup.
 struct BwdGeo {
@@ -288,54 +267,6 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
         }
         wave_sync();
     }
-}
-
-// max over the block of one value per thread (every thread gets the result); `red` holds
-// one float per wave and is free again when the function returns
-__device__ inline float block_max(float v, float* red) {
-    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
-    const int nw = blockDim.x / kWave;
-    __syncthreads();
-    if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = v;
-    __syncthreads();
-    float m = red[0];
-    for (int i = 1; i < nw; ++i) m = fmaxf(m, red[i]);
-    __syncthreads();
-    return m;
-}
-
-__device__ __forceinline__ void absmax_acc(float v, float& m, bool& bad) {
-    v = fabsf(v);
-    bad |= !(v <= FLT_MAX);
-    m = fmaxf(m, v);
-}
-
-// max |p[i]| over [0, n) by the whole block: 4-element vector loads (eight per thread in
-// flight) when p is aligned to 4 elements, element loads for the rest
-template <typename T>
-__device__ inline void absmax_range(const T* p, int64_t n, float& m, bool& bad) {
-    int64_t i0 = 0;
-    if ((reinterpret_cast<uintptr_t>(p) & (4 * sizeof(T) - 1)) == 0) {
-        const int64_t n4 = n / 4, step = blockDim.x;
-        int64_t v = threadIdx.x;
-        for (; v + 7 * step < n4; v += 8 * step) {
-            float q[8][4];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) ld4<T>(p + 4 * (v + u * step), q[u]);
-#pragma unroll
-            for (int u = 0; u < 8; ++u)
-#pragma unroll
-                for (int e = 0; e < 4; ++e) absmax_acc(q[u][e], m, bad);
-        }
-        for (; v < n4; v += step) {
-            float q[4];
-            ld4<T>(p + 4 * v, q);
-#pragma unroll
-            for (int e = 0; e < 4; ++e) absmax_acc(q[e], m, bad);
-        }
-        i0 = n4 * 4;
-    }
-    for (int64_t i = i0 + threadIdx.x; i < n; i += blockDim.x) absmax_acc(ldf<T>(p + i), m, bad);
 }
 
 template <typename IO, typename MT, bool FASTMAP>

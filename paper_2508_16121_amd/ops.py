@@ -156,6 +156,51 @@ def apply_bwd(x, dy, U, s, V, smap, need_dx=True, need_factors=True, need_map=Tr
     return out
 
 
+def apply_grid_bwd(x, dy, U, s, V, smap, grids, gw, need_dx=True, need_factors=True, need_map=True,
+                   need_bias=False, need_grids=True, ws=None):
+    """Gradients through svdlut_apply_grid (svdlut_apply_grid_bwd); returns a dict of the
+    requested ones (dx, dU, ds, dV, dmap, db, dgrids, dgw, dgb)."""
+    _need(x, "x", (torch.float32, torch.float16), 4)
+    _need(dy, "dy", (x.dtype,), 4)
+    if dy.shape != x.shape:
+        raise ValueError("dy must have the shape of x")
+    B, _, H, W = x.shape
+    D, R = _factors(U, s, V, B)
+    _need(smap, "smap", (torch.float32, torch.float16), 4)
+    h, w = smap.shape[2], smap.shape[3]
+    _need(grids, "grids", ndim=5)
+    _need(gw, "gw", ndim=3)
+    K, Ds = grids.shape[1], grids.shape[3]
+    if grids.shape != (B, K, 3, Ds, Ds) or gw.shape != (B, K, 3):
+        raise ValueError("grids must be [B][K][3][Ds][Ds] and gw [B][K][3]")
+    dev = x.device
+    f32 = dict(device=dev, dtype=torch.float32)
+    dx = torch.empty_like(x) if need_dx else None
+    dU = torch.empty_like(U) if need_factors else None
+    ds = torch.empty_like(s) if need_factors else None
+    dV = torch.empty_like(V) if need_factors else None
+    dmap = torch.empty(B, 9, h, w, **f32) if need_map else None
+    db = torch.empty(B, 3, **f32) if need_bias else None
+    dgr = torch.empty_like(grids) if need_grids else None
+    dgw = torch.empty_like(gw) if need_grids else None
+    dgb = torch.empty(B, K, **f32) if need_grids else None
+    lib = _lib.load()
+    if ws is None and (need_factors or need_grids):
+        nbytes = lib.svdlut_apply_grid_bwd_workspace_size(B, D, Ds)
+        ws = torch.empty((nbytes + 3) // 4, **f32)
+    wsb = ws.numel() * ws.element_size() if ws is not None else 0
+    check(lib.svdlut_apply_grid_bwd(_ptr(x), _ptr(dy), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap),
+                                    _DT[smap.dtype], _ptr(grids), _ptr(gw), K, Ds, _ptr(dx), _ptr(dU), _ptr(ds),
+                                    _ptr(dV), _ptr(dmap), _ptr(db), _ptr(dgr), _ptr(dgw), _ptr(dgb),
+                                    B, H, W, h, w, D, R, _ptr(ws), wsb, _stream()), "svdlut_apply_grid_bwd")
+    out = {}
+    for k, v in (("dx", dx), ("dU", dU), ("ds", ds), ("dV", dV), ("dmap", dmap), ("db", db),
+                 ("dgrids", dgr), ("dgw", dgw), ("dgb", dgb)):
+        if v is not None:
+            out[k] = v
+    return out
+
+
 class _ApplyFn(torch.autograd.Function):
     """svdlut_apply forward with svdlut_apply_bwd as its backward."""
 

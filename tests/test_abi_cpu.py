@@ -76,6 +76,15 @@ def test_validation_happens_before_any_hip_call(lib):
     assert lib.svdlut_apply_grid(*gargs, fake, fake, fake, 6, 1, 1, 4, 4, 1, 1, 33, 8, null) == 1
     assert lib.svdlut_apply_grid(*gargs, fake, fake, fake, 6, 34, 1, 4, 4, 1, 1, 33, 8, null) == 1
     assert lib.svdlut_apply_grid(*gargs, fake, fake, fake, 6, 17, 0, 4, 4, 1, 1, 33, 8, null) == 1
+    gb_ = [fake, fake, 0, fake, fake, fake, fake, 0]
+    assert lib.svdlut_apply_grid_bwd(*gb_, null, fake, 6, 17, fake, null, null, null, null, null, null, null, null,
+                                     1, 8, 8, 1, 1, 33, 8, null, 0, null) == 1
+    assert lib.svdlut_apply_grid_bwd(*gb_, fake, fake, 6, 17, fake, null, null, null, null, null, fake, null, null,
+                                     1, 8, 8, 1, 1, 33, 8, fake, 1 << 30, null) == 1
+    assert "all set" in _err(lib)
+    assert lib.svdlut_apply_grid_bwd(*gb_, fake, fake, 6, 17, null, null, null, null, null, null, fake, fake, fake,
+                                     1, 8, 8, 1, 1, 33, 8, fake, 16, null) == 1
+    assert "workspace" in _err(lib)
     # backward: partial factor trio, missing or short workspace
     b = [fake, fake, 0, fake, fake, fake, fake, 0]
     assert lib.svdlut_apply_bwd(*b, fake, fake, null, fake, null, null, 1, 8, 8, 1, 1, 33, 8, fake, 1 << 30, null) == 1

@@ -95,3 +95,62 @@ def test_apply_grid_4k_sampled(svd):
         ref[k % 3] += Psi[k]
     assert np.abs(y[:, ys, xs] - ref).max() <= TOL32
     assert np.isfinite(y).all()
+
+
+# ------------------------------------------------------------------ backward
+def _grid_bwd_ref(x, U, s, V, m, gr, gw, G):
+    """Oracle gradients of sum(G * Y) through the fused forward: LUT part + grid part."""
+    lut = ol.apply_bwd(x, U, s, V, m, G)
+    B = x.shape[0]
+    parts = [og.slice_bwd(x[b], gr[b], gw[b], G[b]) for b in range(B)]
+    ref = dict(lut)
+    ref["dx"] = lut["dx"] + np.stack([p["dx"] for p in parts])
+    ref["dgrids"] = np.stack([p["dg"] for p in parts])
+    ref["dgw"] = np.stack([p["dgw"] for p in parts])
+    ref["dgb"] = np.stack([p["dgb"] for p in parts])
+    return ref
+
+
+def _check_bwd(svd, shape, seed, io=torch.float32, rel=1e-4):
+    B, H, W, D, R, h, w, K, Ds = shape
+    g = np.random.default_rng(seed)
+    x = g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)
+    U, s, V = synth.factors(g, B, D, R)
+    m = synth.spatial_map(g, B, h, w)
+    gr, gw, gb = synth.grids(g, B, K, Ds)
+    G = g.normal(size=(B, 3, H, W)).astype(np.float32)
+    say(f"apply_grid_bwd {shape} io={io}")
+    xd, Gd = dev(x, io), dev(G, io)
+    r = svd.apply_grid_bwd(xd, Gd, dev(U), dev(s), dev(V), dev(m), dev(gr), dev(gw), need_bias=True)
+    ref = _grid_bwd_ref(host(xd), U, s, V, m, gr, gw, host(Gd))
+    names = {"dx": "dx", "dU": "dU", "ds": "ds", "dV": "dV", "dmap": "dmap", "db": "db",
+             "dgrids": "dgrids", "dgw": "dgw", "dgb": "dgb"}
+    for k, rk in names.items():
+        got = host(r[k])
+        want = ref[rk]
+        scale = max(np.abs(want).max(), 1e-12)
+        err = np.abs(got - want).max()
+        assert err <= rel * scale, f"{k}: max-abs {err} vs scale {scale}"
+    return r
+
+
+@pytest.mark.parametrize("shape", [
+    # B, H, W, D, R, h, w, K, Ds
+    (1, 48, 96, 17, 4, 6, 12, 6, 17),
+    (2, 37, 131, 33, 8, 5, 17, 6, 17),    # ragged, width not a multiple of 4
+    (1, 20, 24, 9, 3, 15, 15, 3, 9),      # more than one grid vertex per pixel step (tiny image)
+    (1, 1, 300, 5, 2, 1, 38, 6, 2),       # one row, Ds = 2
+])
+def test_apply_grid_bwd_parity(svd, shape):
+    _check_bwd(svd, shape, seed=sum(shape) + 7)
+
+
+def test_apply_grid_bwd_fp16(svd):
+    _check_bwd(svd, (1, 40, 64, 33, 8, 5, 8, 6, 17), seed=45, io=torch.float16, rel=2e-3)
+
+
+def test_apply_grid_bwd_grid_gradients_reproducible(svd):
+    r1 = _check_bwd(svd, (1, 64, 128, 17, 4, 8, 16, 6, 17), seed=46)
+    r2 = _check_bwd(svd, (1, 64, 128, 17, 4, 8, 16, 6, 17), seed=46)
+    for k in ("dgrids", "dgw", "dgb", "dU", "ds", "dV", "dx"):
+        assert torch.equal(r1[k], r2[k]), k
