@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1")
+    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1,g4,sweep")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run device-to-device copies of one 4K fp32 frame (99.5 MB), the reference "
@@ -227,6 +227,62 @@ def row_c4(svd, torch, synth, args):
             "fwd_roofline": roof(b_fwd, ms_f), "fwd_bwd_roofline": roof(b_fb, ms_fb)}
 
 
+def row_g4(svd, torch, synth, args):
+    """C4's differentiation batch with K = 6 bilateral grids of 17x17: forward + L1 + full backward."""
+    c = synth.diff_batch()
+    B, H, W = c.x.shape[0], c.x.shape[2], c.x.shape[3]
+    npx = B * H * W
+    gr, gw, gb = synth.grids(np.random.default_rng(47), B, 6, 17)
+    sets = []
+    for k in range(N_ROT):
+        d = {a: torch.from_numpy(getattr(c, a)).cuda() for a in ("x", "U", "s", "V", "smap", "target")}
+        d.update(gr=torch.from_numpy(gr).cuda(), gw=torch.from_numpy(gw).cuda(), gb=torch.from_numpy(gb).cuda())
+        d["y"] = torch.empty_like(d["x"])
+        d["ws"] = svd.grid_bwd_workspace(B, 33, 17, "cuda")
+        sets.append(d)
+
+    def fwd_bwd(i):
+        d = sets[i % N_ROT]
+        svd.apply_grid(d["x"], d["U"], d["s"], d["V"], d["smap"], d["gr"], d["gw"], d["gb"], out=d["y"])
+        _, dy = svd.loss(d["y"], d["target"], "l1")
+        svd.apply_grid_bwd(d["x"], dy, d["U"], d["s"], d["V"], d["smap"], d["gr"], d["gw"], ws=d["ws"])
+
+    steps = max(5, args.steps // 4)
+    ms_fb = event_time(fwd_bwd, steps, 3, torch)
+    mapb = B * 9 * 64 * 64 * 4
+    b_fb = npx * 24 + mapb + npx * 36 + npx * 36 + 2 * mapb + npx * 24   # + the grid pass's dx read/write
+    return {"workload": "16x3x512x512 fp32, D=33 R=8, map 9x64x64, K=6 grids 17x17: apply_grid + L1 loss + "
+                        "apply_grid_bwd (dU ds dV dmap dx dgrids dgw dgb)",
+            "fwd_bwd_ms": round(ms_fb, 4), "fwd_bwd_mpix_s": round(npx / (ms_fb * 1e-3) / 1e6, 1),
+            "fwd_bwd_roofline": roof(b_fb, ms_fb)}
+
+
+def row_sweep(svd, torch, synth, args):
+    """4K fp32 apply throughput across LUT sizes D in {17, 33} and ranks R in {1, 4, 8, 16}, and the
+    rank-R truncation error of a dense LUT of the same size (Eckart-Young: the Frobenius error
+    equals the norm of the dropped singular values)."""
+    g = np.random.default_rng(48)
+    xh = synth.image(g, 2160, 3840)[None]
+    mh = synth.spatial_map(g, 1, 270, 480)
+    # four disjoint buffer sets, as for the headline, so the 256 MB cache does not hold the frame
+    bufs = [(torch.from_numpy(xh).cuda(), torch.from_numpy(mh).cuda(), torch.empty(1, 3, 2160, 3840, device="cuda"))
+            for _ in range(N_ROT)]
+    out = {}
+    for D in (17, 33):
+        A = g.uniform(-1, 1, (D, D))
+        sig = np.linalg.svd(A, compute_uv=False)
+        for R in (1, 4, 8, 16):
+            U, s, V = (torch.from_numpy(a).cuda() for a in synth.factors(g, 1, D, R))
+
+            def step(i):
+                x, m, y = bufs[i % N_ROT]
+                svd.apply(x, U, s, V, m, out=y)
+            ms = event_time(step, max(10, args.steps // 4), 3, torch)
+            out[f"D{D}_R{R}"] = {"ms": round(ms, 4), "mpix_s": round(2160 * 3840 / (ms * 1e-3) / 1e6, 1),
+                                 "rel_frobenius_error": round(float(np.sqrt((sig[R:] ** 2).sum() / (sig ** 2).sum())), 5)}
+    return {"workload": "svdlut_apply 1x3x2160x3840 fp32, map 9x270x480; D x R sweep", "points": out}
+
+
 def row_c5(svd, torch, synth, args):
     from paper_2508_16121_amd import generator as G
     g = np.random.default_rng(5)
@@ -301,9 +357,9 @@ def main():
         ms_copy = event_time(lambda i: dst.copy_(src), max(5, args.steps // 4), 2, torch)
         out["copy_probe"] = {"bytes_per_copy": 2 * src.numel() * 4, "ms": round(ms_copy, 5),
                              "gb_s": round(2 * src.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
-    want = {"c1", "c3", "c4", "c5", "g1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
+    want = {"c1", "c3", "c4", "c5", "g1", "g4"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
     rows = {}
-    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1)):
+    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep)):
         if name in want:
             rows[name] = fn(svd, torch, synth, args)
             print(f"row {name} done", file=sys.stderr, flush=True)

@@ -124,6 +124,11 @@ def bwd_workspace(B, D, device):
     return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)
 
 
+def grid_bwd_workspace(B, D, Ds, device):
+    n = _lib.load().svdlut_apply_grid_bwd_workspace_size(B, D, Ds)
+    return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)
+
+
 def apply_bwd(x, dy, U, s, V, smap, need_dx=True, need_factors=True, need_map=True, need_bias=False,
               ws=None):
     """Gradients through svdlut_apply (svdlut_apply_bwd); returns a dict of the requested ones."""
@@ -186,8 +191,7 @@ def apply_grid_bwd(x, dy, U, s, V, smap, grids, gw, need_dx=True, need_factors=T
     dgb = torch.empty(B, K, **f32) if need_grids else None
     lib = _lib.load()
     if ws is None and (need_factors or need_grids):
-        nbytes = lib.svdlut_apply_grid_bwd_workspace_size(B, D, Ds)
-        ws = torch.empty((nbytes + 3) // 4, **f32)
+        ws = grid_bwd_workspace(B, D, Ds, dev)
     wsb = ws.numel() * ws.element_size() if ws is not None else 0
     check(lib.svdlut_apply_grid_bwd(_ptr(x), _ptr(dy), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap),
                                     _DT[smap.dtype], _ptr(grids), _ptr(gw), K, Ds, _ptr(dx), _ptr(dU), _ptr(ds),
