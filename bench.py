@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1,g4,sweep")
+    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1,g4,sweep,u1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run device-to-device copies of one 4K fp32 frame (99.5 MB), the reference "
@@ -182,6 +182,36 @@ def row_g1(svd, torch, synth, args):
     return {"workload": "svdlut_apply_grid 1x3x2160x3840 fp32, D=33 R=8, map 9x270x480, K=6 grids x 3 planes 17x17",
             "ms": round(ms, 5), "kernel_ms": round(ms_kernel, 5), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1),
             "roofline": roof(bytes_alg, ms_kernel)}
+
+
+def row_u1(svd, torch, synth, args):
+    """The paper's unfused original structure at 4K (slicing -> f_s -> 1x1 fusion -> 3D LUT, K = 6
+    grids of 17x17, 33^3 3D LUTs) against the fused pass (svdlut_apply_grid) on the same frame."""
+    c, gr, gw, gb = synth.grid_case(43, 2160, 3840, 33, 8, 270, 480)
+    g = np.random.default_rng(49)
+    K, D3 = 6, 33
+    Wf = np.concatenate([np.eye(3, dtype=np.float32)[None], g.normal(0, 0.1, (1, 3, K)).astype(np.float32)], axis=2)
+    bf = g.normal(0, 0.01, (1, 3)).astype(np.float32)
+    T3 = g.normal(0.5, 0.1, (1, 3, D3, D3, D3)).astype(np.float32)
+    sets = []
+    for k in range(N_ROT):
+        t = [torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in (c.x, gr, gw, gb, Wf, bf, T3)]
+        ws = torch.empty(svd._lib.load().svdlut_unfused_workspace_size(1, 2160, 3840, K, D3) // 4 + 64, device="cuda")
+        sets.append((t, ws, torch.empty_like(t[0])))
+    torch.cuda.synchronize()
+
+    def step(i):
+        t, ws, y = sets[i % N_ROT]
+        svd.unfused_apply(*t, out=y, ws=ws)
+
+    steps = max(10, args.steps // 4)
+    ms = event_time(step, steps, 3, torch)
+    npx = 2160 * 3840
+    per_px = 12 + 4 * K + (12 + 4 * K + 12) + (12 + 12)   # slicing, fusion, 3D LUT passes (B/px)
+    return {"workload": "unfused original structure 1x3x2160x3840 fp32: slicing (K=6 grids 17x17) -> f_s -> "
+                        "1x1 fusion -> 33^3 3D LUT, 4 kernels",
+            "ms": round(ms, 4), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1), "bytes_per_px": per_px,
+            "roofline": roof(npx * per_px, ms)}
 
 
 def row_c1(svd, torch, synth, args):
@@ -394,9 +424,9 @@ def main():
         ms_copy = event_time(lambda i: dst.copy_(src), max(5, args.steps // 4), 2, torch)
         out["copy_probe"] = {"bytes_per_copy": 2 * src.numel() * 4, "ms": round(ms_copy, 5),
                              "gb_s": round(2 * src.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
-    want = {"c1", "c3", "c4", "c5", "g1", "g4"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
+    want = {"c1", "c3", "c4", "c5", "g1", "g4", "sweep", "u1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
     rows = {}
-    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep)):
+    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep), ("u1", row_u1)):
         if name in want:
             rows[name] = fn(svd, torch, synth, args)
             print(f"row {name} done", file=sys.stderr, flush=True)

@@ -110,6 +110,27 @@ svdlut_status svdlut_apply_grid(const void* x, void* y, svdlut_dtype io, const f
 
 
 /*
+ * svdlut_unfused_apply — the unfused "original structure" the paper starts from (Sec.
+ * "Preliminary"), as a baseline for the fused pass: slicing of K bilateral grids into
+ * spatial-feature planes f_s (Eq. slicing; Psi^k as in svdlut_apply_grid, one plane per grid,
+ * written to the workspace), the 1x1 convolution X_bar = Wf . concat(X, f_s) + bf written to
+ * the workspace (Eq. fusion; input channels ordered r, g, b, f_0 .. f_{K-1}), and the 3D-LUT
+ * transform Y_c = trilinear lookup of T3[c] at X_bar (Eq. coloren; LUT indexed [i_r][i_g][i_b],
+ * the decode of svdlut_apply with D vertices).  float32 only.
+ *   x, y: [B][3][H][W];  grids [B][K][3][Ds][Ds], gw [B][K][3], gb [B][K];  Wf [B][3][K+3],
+ *   bf [B][3];  T3 [B][3][D][D][D].
+ *   ws: at least svdlut_unfused_workspace_size(B, H, W, K, D) bytes, 256-byte aligned,
+ *   caller-owned (holds f_s, X_bar and the packed 3D LUTs).
+ * Errors: EINVAL for a null pointer, bad sizes or a short workspace; EUNSUPPORTED when the K
+ * grids do not fit 64 KB of LDS.
+ */
+size_t svdlut_unfused_workspace_size(int32_t B, int32_t H, int32_t W, int32_t K, int32_t D);
+svdlut_status svdlut_unfused_apply(const float* x, float* y, const float* grids, const float* gw,
+                                   const float* gb, const float* Wf, const float* bf, const float* T3,
+                                   int32_t K, int32_t Ds, int32_t D, int32_t B, int32_t H, int32_t W,
+                                   void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * svdlut_apply_bwd — gradients of a scalar loss through svdlut_apply, given
  * dy = dL/dY [B][3][H][W] (dtype io).  By the chain rule of the forward:
  *   dT_l[i_a + a][i_b + b] += dy_c * S_l * w_alpha(a) * w_beta(b)   (then dU, ds, dV below)

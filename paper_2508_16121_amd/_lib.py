@@ -33,6 +33,8 @@ SIGS = {
                                 I32, I32, I32, I32, I32, I32, I32, P]),
     "svdlut_apply_bwd_workspace_size": (SZ, [I32, I32]),
     "svdlut_apply_grid_bwd_workspace_size": (SZ, [I32, I32, I32]),
+    "svdlut_unfused_workspace_size": (SZ, [I32, I32, I32, I32, I32]),
+    "svdlut_unfused_apply": (I32, [P, P, P, P, P, P, P, P, I32, I32, I32, I32, I32, I32, P, SZ, P]),
     "svdlut_apply_grid_bwd": (I32, [P, P, I32, P, P, P, P, I32, P, P, I32, I32, P, P, P, P, P, P, P, P, P,
                                     I32, I32, I32, I32, I32, I32, I32, P, SZ, P]),
     "svdlut_apply_bwd": (I32, [P, P, I32, P, P, P, P, I32, P, P, P, P, P, P,

@@ -164,6 +164,31 @@ svdlut_status svdlut_apply_grid(const void* x, void* y, svdlut_dtype io, const f
                       stream);
 }
 
+size_t svdlut_unfused_workspace_size(int32_t B, int32_t H, int32_t W, int32_t K, int32_t D) {
+    if (B < 1 || !dims_ok(H) || !dims_ok(W) || K < 1 || K > kMaxGrids || D < 2 || D > kMaxD) return 0;
+    return unfused_workspace_bytes(B, H, W, K, D);
+}
+
+svdlut_status svdlut_unfused_apply(const float* x, float* y, const float* grids, const float* gw,
+                                   const float* gb, const float* Wf, const float* bf, const float* T3,
+                                   int32_t K, int32_t Ds, int32_t D, int32_t B, int32_t H, int32_t W,
+                                   void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!x || !y || !grids || !gw || !gb || !Wf || !bf || !T3 || !ws)
+        return fail(SVDLUT_EINVAL, "unfused_apply: null pointer");
+    if (B < 1 || !dims_ok(H) || !dims_ok(W)) return fail(SVDLUT_EINVAL, "unfused_apply: bad B, H or W");
+    if (K < 1 || K > kMaxGrids) return fail(SVDLUT_EINVAL, "unfused_apply: K must be in [1, 12]");
+    if (Ds < 2 || Ds > kMaxDs) return fail(SVDLUT_EINVAL, "unfused_apply: Ds must be in [2, 33]");
+    if (D < 2 || D > kMaxD) return fail(SVDLUT_EINVAL, "unfused_apply: D must be in [2, 40]");
+    if (sizeof(float) * static_cast<size_t>(K) * 3 * Ds * grid_plane_stride(Ds) > 65536)
+        return fail(SVDLUT_EUNSUPPORTED, "unfused_apply: K grids of Ds^2 planes exceed 64 KB of LDS");
+    if (ws_bytes < unfused_workspace_bytes(B, H, W, K, D))
+        return fail(SVDLUT_EINVAL, "unfused_apply: workspace smaller than svdlut_unfused_workspace_size()");
+    UnfusedLaunch a{};
+    a.x = x; a.y = y; a.grids = grids; a.gw = gw; a.gb = gb; a.Wf = Wf; a.bf = bf; a.T3 = T3; a.ws = ws;
+    a.B = B; a.H = H; a.W = W; a.K = K; a.Ds = Ds; a.D = D;
+    return launch_unfused(a, stream);
+}
+
 size_t svdlut_apply_grid_bwd_workspace_size(int32_t B, int32_t D, int32_t Ds) {
     if (B < 1 || D < 2 || D > kMaxD || Ds < 2 || Ds > kMaxDs) return 0;
     return ((bwd_workspace_bytes(B, D) + 255) & ~static_cast<size_t>(255)) + grid_bwd_workspace_bytes(B, Ds);

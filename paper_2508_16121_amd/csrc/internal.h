@@ -117,6 +117,22 @@ struct GridBwdLaunch {
 size_t grid_bwd_workspace_bytes(int B, int Ds);
 svdlut_status launch_grid_bwd(const GridBwdLaunch& a, hipStream_t st);
 
+// Unfused original-structure baseline (slicing -> f_s -> 1x1 fusion -> 3D LUT), float32.
+struct UnfusedLaunch {
+    const float* x;
+    float* y;
+    const float* grids;            // [B][K][3][Ds][Ds]
+    const float* gw;               // [B][K][3]
+    const float* gb;               // [B][K]
+    const float* Wf;               // [B][3][K+3]
+    const float* bf;               // [B][3]
+    const float* T3;               // [B][3][D][D][D]
+    void* ws;                      // unfused_workspace_bytes(B, H, W, K, D)
+    int32_t B, H, W, K, Ds, D;
+};
+size_t unfused_workspace_bytes(int B, int H, int W, int K, int D);
+svdlut_status launch_unfused(const UnfusedLaunch& a, hipStream_t st);
+
 // ---------------------------------------------------------------- generator
 svdlut_status launch_loss(const void* y, const void* t, svdlut_dtype io, int64_t n, int kind,
                           float* loss, void* dy, float* partial, int nblocks, hipStream_t st);

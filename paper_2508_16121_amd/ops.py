@@ -205,6 +205,31 @@ def apply_grid_bwd(x, dy, U, s, V, smap, grids, gw, need_dx=True, need_factors=T
     return out
 
 
+def unfused_apply(x, grids, gw, gb, Wf, bf, T3, out=None, ws=None):
+    """The unfused original structure (svdlut_unfused_apply): slicing -> f_s -> 1x1 fusion
+    -> 3D LUT, float32.  grids [B][K][3][Ds][Ds], gw [B][K][3], gb [B][K], Wf [B][3][K+3],
+    bf [B][3], T3 [B][3][D][D][D]."""
+    _need(x, "x", ndim=4)
+    B, _, H, W = x.shape
+    for t, name, nd in ((grids, "grids", 5), (gw, "gw", 3), (gb, "gb", 2), (Wf, "Wf", 3), (bf, "bf", 2),
+                        (T3, "T3", 5)):
+        _need(t, name, ndim=nd)
+    K, Ds, D = grids.shape[1], grids.shape[3], T3.shape[2]
+    if (grids.shape != (B, K, 3, Ds, Ds) or gw.shape != (B, K, 3) or gb.shape != (B, K)
+            or Wf.shape != (B, 3, K + 3) or bf.shape != (B, 3) or T3.shape != (B, 3, D, D, D)):
+        raise ValueError("unfused_apply: inconsistent shapes")
+    lib = _lib.load()
+    if ws is None:
+        ws = torch.empty(lib.svdlut_unfused_workspace_size(B, H, W, K, D) // 4 + 64, dtype=torch.float32,
+                         device=x.device)
+    if out is None:
+        out = torch.empty_like(x)
+    check(lib.svdlut_unfused_apply(_ptr(x), _ptr(out), _ptr(grids), _ptr(gw), _ptr(gb), _ptr(Wf), _ptr(bf),
+                                   _ptr(T3), K, Ds, D, B, H, W, _ptr(ws), ws.numel() * 4, _stream()),
+          "svdlut_unfused_apply")
+    return out
+
+
 class _ApplyFn(torch.autograd.Function):
     """svdlut_apply forward with svdlut_apply_bwd as its backward."""
 

@@ -85,6 +85,12 @@ def test_validation_happens_before_any_hip_call(lib):
     assert lib.svdlut_apply_grid_bwd(*gb_, fake, fake, 6, 17, null, null, null, null, null, null, fake, fake, fake,
                                      1, 8, 8, 1, 1, 33, 8, fake, 16, null) == 1
     assert "workspace" in _err(lib)
+    # unfused baseline: null pointers, bad sizes, short workspace
+    assert lib.svdlut_unfused_apply(null, fake, fake, fake, fake, fake, fake, fake, 6, 17, 33, 1, 8, 8, fake, 1 << 30, null) == 1
+    assert lib.svdlut_unfused_apply(fake, fake, fake, fake, fake, fake, fake, fake, 6, 17, 41, 1, 8, 8, fake, 1 << 30, null) == 1
+    assert lib.svdlut_unfused_apply(fake, fake, fake, fake, fake, fake, fake, fake, 12, 33, 33, 1, 8, 8, fake, 1 << 30, null) == 2
+    assert lib.svdlut_unfused_apply(fake, fake, fake, fake, fake, fake, fake, fake, 6, 17, 33, 1, 8, 8, fake, 16, null) == 1
+    assert "workspace" in _err(lib)
     # backward: partial factor trio, missing or short workspace
     b = [fake, fake, 0, fake, fake, fake, fake, 0]
     assert lib.svdlut_apply_bwd(*b, fake, fake, null, fake, null, null, 1, 8, 8, 1, 1, 33, 8, fake, 1 << 30, null) == 1

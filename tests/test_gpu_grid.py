@@ -154,3 +154,29 @@ def test_apply_grid_bwd_grid_gradients_reproducible(svd):
     r2 = _check_bwd(svd, (1, 64, 128, 17, 4, 8, 16, 6, 17), seed=46)
     for k in ("dgrids", "dgw", "dgb", "dU", "ds", "dV", "dx"):
         assert torch.equal(r1[k], r2[k]), k
+
+
+# ------------------------------------------------------------------ unfused original structure
+def _unfused_inputs(g, B, H, W, K, Ds, D):
+    x = g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)
+    gr, gw, gb = synth.grids(g, B, K, Ds)
+    Wf = np.concatenate([np.broadcast_to(np.eye(3), (B, 3, 3)), g.normal(0, 0.1, (B, 3, K))], axis=2)
+    Wf = np.ascontiguousarray(Wf, dtype=np.float32)
+    bf = g.normal(0, 0.01, (B, 3)).astype(np.float32)
+    t = np.linspace(0.0, 1.0, D)
+    ident = np.stack([np.broadcast_to(a, (D, D, D)) for a in (t[:, None, None], t[None, :, None], t[None, None, :])])
+    T3 = (ident[None] + g.normal(0, 0.05, (B, 3, D, D, D))).astype(np.float32)
+    return x, gr, gw, gb, Wf, bf, T3
+
+
+@pytest.mark.parametrize("shape", [(1, 48, 96, 6, 17, 17), (2, 37, 131, 3, 5, 33), (1, 1, 300, 6, 2, 9)])
+def test_unfused_original_structure_parity(svd, shape):
+    from oracle import unfused as ou
+    B, H, W, K, Ds, D = shape
+    g = np.random.default_rng(sum(shape) + 60)
+    x, gr, gw, gb, Wf, bf, T3 = _unfused_inputs(g, B, H, W, K, Ds, D)
+    say(f"unfused {shape}")
+    y = host(svd.unfused_apply(*(dev(a) for a in (x, gr, gw, gb, Wf, bf, T3))))
+    ref = np.stack([ou.original_structure(x[b], gr[b], gw[b], gb[b], Wf[b], bf[b], T3[b])[0] for b in range(B)])
+    err = np.abs(y - ref).max()
+    assert err <= TOL32, f"max-abs {err}"
