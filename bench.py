@@ -1,6 +1,6 @@
 """Benchmark of the 2D-LUT hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows all|none|c1,c3,c4,c5]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows all|none|c1,c3,c4,c5,g1,g4,sweep,u1,p1]
 
 Headline (`value`): svdlut_apply on one 3840x2160 float32 frame (33x33 LUTs at rank 8,
 reconstruction fused, 480x270 spatial map), in Mpix/s, inputs resident in HBM.  Each timed
@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1,g4,sweep,u1")
+    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1,g4,sweep,u1,p1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run device-to-device copies of one 4K fp32 frame (99.5 MB), the reference "
@@ -382,6 +382,44 @@ def row_c5(svd, torch, synth, args):
             "train_step_ms_batch16": round(ms_train, 4), "train_steps_s": round(1000.0 / ms_train, 1)}
 
 
+def row_p1(svd, torch, synth, args):
+    """The paper's whole model at 4K: its generator (m = 8 backbone, four FC generators) then
+    the fused slicing + 2D-LUT transform with scalar LUT weights and K = 6 grids."""
+    from paper_2508_16121_amd import paper_model as PM
+    g = np.random.default_rng(7)
+    img = synth.image(g, 2160, 3840)[None]
+    gen = PM.PaperGenerator(33, 8, 6, 17, seed=0)
+    res = {"workload": "paper model (160,478 params): 3x2160x3840 fp32 -> downsample 256 -> 5 conv blocks (bf16 MFMA, "
+                       "LeakyReLU, instance norm) -> pool -> 4 FC generators -> svdlut_apply_grid (K=6 grids 17x17, "
+                       "1x1 LUT-weight map); training step batch 16 at 256x256 with dropout (MSE, Adam lr 1e-4)",
+           "params": int(gen.n), "paper_v100_ms_4k": 1.38}
+    steps = max(10, args.steps // 4)
+    for B in (1, 8):
+        x = torch.from_numpy(np.concatenate([img] * B)).cuda()
+        y = torch.empty_like(x)
+        box = {}
+
+        def infer(i):
+            o = gen.forward(x)
+            box["o"] = o
+            svd.apply_grid(x, o["U"], o["s"], o["V"], o["lut_w"], o["grids"], o["gw"], o["gb"], bias=o["lut_b"], out=y)
+
+        ms = event_time(infer, steps, 3, torch)
+        ms_gen = event_time(lambda i: gen.forward(x), steps, 3, torch)
+        o = box["o"]
+        ms_tr = event_time(lambda i: svd.apply_grid(x, o["U"], o["s"], o["V"], o["lut_w"], o["grids"], o["gw"],
+                                                    o["gb"], bias=o["lut_b"], out=y), steps, 3, torch)
+        res[f"b{B}"] = {"ms": round(ms, 4), "generator_ms": round(ms_gen, 4), "transform_ms": round(ms_tr, 4),
+                        "mpix_s": round(B * 3840 * 2160 / (ms * 1e-3) / 1e6, 1)}
+    xb = torch.rand(16, 3, 256, 256, device="cuda")
+    tb = torch.rand(16, 3, 256, 256, device="cuda")
+    tr = PM.PaperTrainer(PM.PaperGenerator(33, 8, 6, 17, seed=1), lr=1e-4)
+    ms_train = event_time(lambda i: tr.step(xb, tb), max(10, args.steps // 2), 3, torch)
+    res["train_step_ms_batch16"] = round(ms_train, 4)
+    res["train_steps_s"] = round(1000.0 / ms_train, 1)
+    return res
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -424,9 +462,9 @@ def main():
         ms_copy = event_time(lambda i: dst.copy_(src), max(5, args.steps // 4), 2, torch)
         out["copy_probe"] = {"bytes_per_copy": 2 * src.numel() * 4, "ms": round(ms_copy, 5),
                              "gb_s": round(2 * src.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
-    want = {"c1", "c3", "c4", "c5", "g1", "g4", "sweep", "u1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
+    want = {"c1", "c3", "c4", "c5", "g1", "g4", "sweep", "u1", "p1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
     rows = {}
-    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep), ("u1", row_u1)):
+    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep), ("u1", row_u1), ("p1", row_p1)):
         if name in want:
             rows[name] = fn(svd, torch, synth, args)
             print(f"row {name} done", file=sys.stderr, flush=True)

@@ -281,6 +281,55 @@ svdlut_status svdlut_generator_bwd(const float* params, const float* dU, const f
                                    void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * The paper's own generator (supplementary Sec. "Details of Network Structure", Tables
+ * backbone, gen_lut, gen_lut_weight, gen_bilateral, gen_bilateral_weight; with K = 6,
+ * Ds = 17, D = 33, R = 8 it has the 160,478 parameters of the component ablation, with K = 0
+ * the 109,332 of its LUT-only model):
+ *   bilinear downsample to 256x256 (half-pixel centres, no antialias)
+ *   5 blocks, m = 8: conv3x3 stride 2 pad 1 (+ bias) -> LeakyReLU(0.2) -> instance norm
+ *     (per image and channel, biased variance, eps 1e-5, learned scale and shift; not in
+ *     block 5): 3 -> 8 -> 16 -> 32 -> 64 -> 64 channels, 256^2 -> 8^2
+ *   dropout 0.5 (keep_mask), 4x4 average pooling to 2x2, flattened to 256 features in
+ *     NCHW order (feature 4c + 2py + px)
+ *   generators, each FC 256 -> 8 then FC 8 -> n (no activation between):
+ *     H_t  n = 9(2DR + R): [U (9 x D x R) | S (9 x R) | V (9 x D x R)], LUT l = 3c + p
+ *     H_tw n = 12: per output channel c, (w_rg, w_rb, w_gb, b^c)
+ *     H_s  n = 3 K Ds^2 (only when K > 0): grids [K][3][Ds][Ds], planes (xy, xc, yc)
+ *     H_sw n = 4K (only when K > 0): per grid k, (w_xy, w_xc, w_yc, b^k)
+ * The outputs feed svdlut_apply_grid (or svdlut_apply when K = 0) directly: lut_w is its
+ * 9 x 1 x 1 map (h = w = 1), lut_b its bias, grids/gw/gb its grid arguments.
+ * Convolutions run on bf16 matrix cores with fp32 accumulation; the normalised activations
+ * between blocks are stored as bf16; everything else is fp32.
+ * params: float32 vector of svdlut_paper_generator_param_count(D, R, K, Ds) values, in order
+ *   conv1.w [8][3][3][3], conv1.b [8], norm1.scale [8], norm1.shift [8], conv2 ... norm4,
+ *   conv5.w [64][3][3][64], conv5.b [64], then per generator (t, tw, s, sw)
+ *   fc1.w [8][256], fc1.b [8], fc2.w [n][8], fc2.b [n].
+ * keep_mask (nullable): uint8 [B][64][8][8] (1 keep, 0 drop); kept values are scaled by 2.
+ *   NULL is evaluation mode (no dropout).  The backward must get the forward's mask.
+ * ws: svdlut_paper_generator_workspace_size(B, D, R, K, Ds) bytes holding the last
+ *   forward's activations; the backward reads them (same ws, same parameters, same B).
+ * Forward outputs (float32): U, V [B][9][D][R], s [B][9][R], lut_w [B][9], lut_b [B][3],
+ *   grids [B][K][3][Ds][Ds], gw [B][K][3], gb [B][K] (grid outputs ignored and nullable when
+ *   K = 0).  Backward inputs have the same shapes; a NULL gradient counts as zero.  grads
+ *   (out) has the layout of params and is overwritten.
+ * K in [0, 12]; Ds in [2, 33] when K > 0; D in [2, 40]; R in [1, 64].
+ */
+size_t svdlut_paper_generator_param_count(int32_t D, int32_t R, int32_t K, int32_t Ds);
+size_t svdlut_paper_generator_workspace_size(int32_t B, int32_t D, int32_t R, int32_t K, int32_t Ds);
+svdlut_status svdlut_paper_generator_fwd(const float* params, const void* x, svdlut_dtype io,
+                                         int32_t B, int32_t H, int32_t W, int32_t D, int32_t R,
+                                         int32_t K, int32_t Ds, const uint8_t* keep_mask,
+                                         float* U, float* s, float* V, float* lut_w, float* lut_b,
+                                         float* grids, float* gw, float* gb,
+                                         void* ws, size_t ws_bytes, hipStream_t stream);
+svdlut_status svdlut_paper_generator_bwd(const float* params, const uint8_t* keep_mask,
+                                         const float* dU, const float* ds, const float* dV,
+                                         const float* dlut_w, const float* dlut_b,
+                                         const float* dgrids, const float* dgw, const float* dgb,
+                                         float* grads, int32_t B, int32_t D, int32_t R, int32_t K,
+                                         int32_t Ds, void* ws, size_t ws_bytes, hipStream_t stream);
+
+/*
  * svdlut_adam_step — one step of standard Adam (the paper trains with Adam, Sec.
  * "Application Settings"), in place on n float32 values:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

@@ -51,6 +51,11 @@ SIGS = {
     "svdlut_generator_workspace_size": (SZ, [I32, I32, I32]),
     "svdlut_generator_fwd": (I32, [P, P, I32, I32, I32, I32, I32, I32, P, P, P, P, P, SZ, P]),
     "svdlut_generator_bwd": (I32, [P, P, P, P, P, P, I32, I32, I32, P, SZ, P]),
+    "svdlut_paper_generator_param_count": (SZ, [I32, I32, I32, I32]),
+    "svdlut_paper_generator_workspace_size": (SZ, [I32, I32, I32, I32, I32]),
+    "svdlut_paper_generator_fwd": (I32, [P, P, I32, I32, I32, I32, I32, I32, I32, I32, P, P, P, P, P, P, P, P, P,
+                                         P, SZ, P]),
+    "svdlut_paper_generator_bwd": (I32, [P, P, P, P, P, P, P, P, P, P, P, I32, I32, I32, I32, I32, P, SZ, P]),
     "svdlut_adam_step": (I32, [P, P, P, P, I64, FL, FL, FL, FL, I32, P]),
 }
 

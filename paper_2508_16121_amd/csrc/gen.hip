@@ -177,8 +177,6 @@ struct WS {
     float* da[kConvs];           // da[i] = gradient w.r.t. activation i (i = 1..4), fp32 NHWC
 };
 
-size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
-
 size_t carve_ws(char* base, int B, int D, int R, WS* w) {
     size_t off = 0;
     for (int i = 0; i <= kConvs; ++i) {

@@ -332,6 +332,8 @@ void gemm_nt(int ncols, AL al, BL bl, EP ep, int M, int K, int splitk, hipStream
     else gemm<4>(al, bl, ep, M, ncols, K, splitk, st);
 }
 
+size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
 int wgrad_split(int M) { return std::max(1, std::min(256, M / 512)); }
 
 template <class DZ>

@@ -14,3 +14,36 @@ def pytest_configure(config):
 
 def pytest_report_header(config):
     return f"repo root: {ROOT}"
+
+
+# ------------------------------------------------------------------ training pairs
+N_TRAIN, N_HELD = 1024, 128
+HELD0 = 100_000
+
+
+def make_pairs(first, count):
+    """Synthetic degrade -> restore pairs from the oracle (inputs, targets) as float32 arrays."""
+    from concurrent.futures import ThreadPoolExecutor
+
+    import numpy as np
+
+    from oracle import pairs as op
+    with ThreadPoolExecutor(16) as ex:
+        res = list(ex.map(op.make_pair, range(first, first + count)))
+    return np.stack([r[0] for r in res]), np.stack([r[1] for r in res])
+
+
+@pytest.fixture(scope="session")
+def pair_data():
+    """Training pairs 0..N_TRAIN-1 and held-out pairs from HELD0, on the GPU (shared by the
+    training tests of both generators)."""
+    import time
+
+    import torch
+    print("generating training pairs", flush=True)
+    t = time.time()
+    xtr, ttr = make_pairs(0, N_TRAIN)
+    xte, tte = make_pairs(HELD0, N_HELD)
+    print(f"pairs ready in {time.time() - t:.1f}s", flush=True)
+    cuda = lambda a: torch.from_numpy(a).cuda()
+    return cuda(xtr), cuda(ttr), cuda(xte), cuda(tte)

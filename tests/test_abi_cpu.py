@@ -116,6 +116,32 @@ def test_validation_happens_before_any_hip_call(lib):
     assert lib.svdlut_generator_bwd(fake, null, fake, fake, fake, fake, 1, 33, 8, fake, 1 << 30, null) == 1
 
 
+def test_paper_generator_validation(lib):
+    null = None
+    fake = C.c_void_p(0x1000)
+    big = 1 << 30
+
+    def fwd(params=fake, io=0, B=1, H=256, W=256, D=33, R=8, K=6, Ds=17, grids=fake, ws_bytes=big):
+        return lib.svdlut_paper_generator_fwd(params, fake, io, B, H, W, D, R, K, Ds, null, fake, fake, fake, fake,
+                                              fake, grids, fake, fake, fake, ws_bytes, null)
+    assert fwd(params=null) == 1 and "null" in _err(lib)
+    assert fwd(io=7) == 2
+    assert fwd(B=0) == 1
+    assert fwd(K=13) == 1
+    assert fwd(Ds=1) == 1
+    assert fwd(D=41) == 1
+    assert fwd(grids=null) == 1 and "grid" in _err(lib)
+    assert fwd(ws_bytes=16) == 1 and "workspace" in _err(lib)
+
+    def bwd(params=fake, grads=fake, B=1, K=6, ws_bytes=big):
+        return lib.svdlut_paper_generator_bwd(params, null, fake, fake, fake, fake, fake, fake, fake, fake, grads,
+                                              B, 33, 8, K, 17, fake, ws_bytes, null)
+    assert bwd(grads=null) == 1
+    assert bwd(B=0) == 1
+    assert bwd(K=-1) == 1
+    assert bwd(ws_bytes=16) == 1
+
+
 def test_size_queries(lib):
     assert lib.svdlut_generator_param_count(33, 8) == 872513
     assert lib.svdlut_generator_param_count(17, 4) == 250217 + 9 * 140 * 129
@@ -124,3 +150,9 @@ def test_size_queries(lib):
     assert lib.svdlut_apply_bwd_workspace_size(0, 33) == 0
     assert lib.svdlut_loss_workspace_size(1000) >= 4
     assert lib.svdlut_version().startswith(b"svdlut")
+    # the paper's generator: the component-ablation counts (full model, LUT-only model)
+    assert lib.svdlut_paper_generator_param_count(33, 8, 6, 17) == 160478
+    assert lib.svdlut_paper_generator_param_count(33, 8, 0, 17) == 109332
+    assert lib.svdlut_paper_generator_param_count(33, 8, 13, 17) == 0
+    assert lib.svdlut_paper_generator_workspace_size(8, 33, 8, 6, 17) > 0
+    assert lib.svdlut_paper_generator_workspace_size(0, 33, 8, 6, 17) == 0

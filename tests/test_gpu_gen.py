@@ -4,14 +4,12 @@ fallback on held-out synthetic degrade->restore pairs."""
 import math
 import os
 import time
-from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 import torch
 
 from oracle import generator as og
-from oracle import pairs as op
 
 pytestmark = pytest.mark.gpu
 
@@ -111,25 +109,9 @@ def test_adam_parity(svd, G):
 
 
 # ------------------------------------------------------------------ training
-N_TRAIN, N_HELD = 1024, 128
-HELD0 = 100_000
-
-
-def make_pairs(first, count):
-    with ThreadPoolExecutor(16) as ex:
-        res = list(ex.map(op.make_pair, range(first, first + count)))
-    return np.stack([r[0] for r in res]), np.stack([r[1] for r in res])
-
-
 @pytest.fixture(scope="module")
-def data():
-    say("generating training pairs")
-    t = time.time()
-    xtr, ttr = make_pairs(0, N_TRAIN)
-    xte, tte = make_pairs(HELD0, N_HELD)
-    say(f"pairs ready in {time.time() - t:.1f}s")
-    cuda = lambda a: torch.from_numpy(a).cuda()
-    return cuda(xtr), cuda(ttr), cuda(xte), cuda(tte)
+def data(pair_data):
+    return pair_data
 
 
 def psnr(y, t):

@@ -1,0 +1,209 @@
+"""GPU parity of the paper's own generator (svdlut_paper_generator_fwd/bwd, bf16-MFMA
+convolutions, instance norm, dropout mask, FC generators) against its fp64 oracle in the
+bf16-mirror mode; the whole paper model (generator -> fused slicing + LUT transform with
+scalar LUT weights) against the transform oracle; and its training gain on held-out
+synthetic degrade -> restore pairs."""
+import math
+import time
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import grid as ogr
+from oracle import paper_generator as pg
+
+pytestmark = pytest.mark.gpu
+
+D, R, Ds = 33, 8, 17
+
+
+@pytest.fixture(scope="module")
+def PM():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    from paper_2508_16121_amd import paper_model
+    return paper_model
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.detach().float().cpu().numpy().astype(np.float64)
+
+
+def rand_params(seed, K):
+    g = np.random.default_rng(seed)
+    P = {}
+    for name, shp in pg.param_shapes(D, R, K, Ds):
+        if name.startswith("conv") and name.endswith(".w"):
+            P[name] = g.normal(0, np.sqrt(2.0 / np.prod(shp[1:])), shp)
+        elif name.endswith(".g"):
+            P[name] = g.uniform(0.5, 1.5, shp)
+        else:
+            P[name] = g.normal(0, 0.1, shp)
+    return P
+
+
+def rel_close(got, ref, tol, what):
+    scale = max(np.abs(ref).max(), 1e-30)
+    err = np.abs(got - ref).max()
+    assert err <= tol * scale, f"{what}: max-abs {err:.3e} > {tol} x {scale:.3e}"
+
+
+def max_rel(got, ref):
+    return np.abs(got - ref).max() / max(np.abs(ref).max(), 1e-30)
+
+
+def fro_rel(got, ref):
+    return np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-30)
+
+
+def mask_for(g, B):
+    return (g.uniform(size=(B, 64, 8, 8)) < 0.5).astype(np.uint8)
+
+
+def gpu_out_to_oracle_keys(o):
+    r = {k: host(v) for k, v in o.items()}
+    r["lut_w"] = r["lut_w"].reshape(r["lut_w"].shape[0], 9)
+    return r
+
+
+@pytest.mark.parametrize("K,hw,use_mask", [(6, (256, 256), True), (6, (300, 280), False), (0, (200, 330), True),
+                                           (3, (64, 64), True)])
+def test_paper_generator_forward_parity(PM, K, hw, use_mask):
+    say(f"paper generator forward K={K} hw={hw} mask={use_mask}")
+    P = rand_params(100 + K, K)
+    g = np.random.default_rng(101)
+    x = g.uniform(0, 1, (2, 3) + hw).astype(np.float32)
+    m = mask_for(g, 2) if use_mask else None
+    gen = PM.PaperGenerator(D, R, K, Ds, params=pg.flatten(P, D, R, K, Ds).astype(np.float32))
+    o = gen.forward(torch.from_numpy(x).cuda(), None if m is None else torch.from_numpy(m).cuda())
+    ref, _ = pg.forward(P, x, D, R, K, Ds, mask=m, mixed=True)
+    got = gpu_out_to_oracle_keys(o)
+    assert set(got) == set(ref)
+    for k in ref:
+        rel_close(got[k], ref[k], 2e-2, k)
+
+
+@pytest.mark.parametrize("K,use_mask", [(6, True), (0, False)])
+def test_paper_generator_backward_parity(PM, K, use_mask):
+    """Parameter gradients vs the bf16-mirror oracle.  The mirror cannot take every bf16
+    rounding and LeakyReLU branch decision the way the fp32-accumulating kernels do: a
+    decision that flips in an early block moves many later values by one bf16 step and
+    occasionally flips a LeakyReLU slope (1 vs 0.2) of one term.  The bar is therefore tied
+    to the size of the bf16 effect itself: for every tensor the GPU must be at most half as
+    far from the mirror as the mirror is from the exact fp64 network (relative Frobenius
+    norm), no element may be off by more than 15 % of the tensor's largest value, and the
+    FC-generator gradients, which see the convolutions only through the pooled features,
+    must agree to 2e-3.  A wrong index, sign, slope or dropped term moves a tensor by far
+    more than the bf16 effect (typically 5-50 % here)."""
+    say(f"paper generator backward K={K} mask={use_mask}")
+    P = rand_params(200 + K, K)
+    g = np.random.default_rng(201)
+    B = 3
+    x = g.uniform(0, 1, (B, 3, 256, 256)).astype(np.float32)
+    m = mask_for(g, B) if use_mask else None
+    gen = PM.PaperGenerator(D, R, K, Ds, params=pg.flatten(P, D, R, K, Ds).astype(np.float32))
+    mt = None if m is None else torch.from_numpy(m).cuda()
+    o = gen.forward(torch.from_numpy(x).cuda(), mt)
+    up = {k: g.normal(0, 1, tuple(v.shape)).astype(np.float32) for k, v in o.items()}
+    grads = gen.backward({k: torch.from_numpy(v).cuda() for k, v in up.items()}, mt)
+    _, cache = pg.forward(P, x, D, R, K, Ds, mask=m, mixed=True)
+    up_o = dict(up)
+    up_o["lut_w"] = up["lut_w"].reshape(B, 9)
+    ref = pg.backward(P, cache, up_o, D, R, K, Ds, mask=m, mixed=True)
+    _, cache_x = pg.forward(P, x, D, R, K, Ds, mask=m, mixed=False)
+    exact = pg.backward(P, cache_x, up_o, D, R, K, Ds, mask=m, mixed=False)
+    got = pg.unflatten(host(grads), D, R, K, Ds)
+    for k in ref:
+        say(f"  {k:12s} gpu-mixed max {max_rel(got[k], ref[k]):.2e} fro {fro_rel(got[k], ref[k]):.2e} | "
+            f"mixed-exact max {max_rel(ref[k], exact[k]):.2e} fro {fro_rel(ref[k], exact[k]):.2e}")
+    for k in ref:
+        f_gm, f_me = fro_rel(got[k], ref[k]), fro_rel(ref[k], exact[k])
+        assert f_gm <= max(0.5 * f_me, 1e-5), f"{k}: |gpu - mirror| {f_gm:.2e} vs |mirror - exact| {f_me:.2e}"
+        assert max_rel(got[k], ref[k]) <= 0.15, k
+        if not k.startswith(("conv", "in")):
+            assert max_rel(got[k], ref[k]) <= 2e-3, k
+
+
+def test_paper_generator_missing_gradient_is_zero(PM):
+    """A NULL upstream gradient counts as zero: the grid generators then get no gradient."""
+    K = 6
+    P = rand_params(300, K)
+    g = np.random.default_rng(301)
+    x = torch.from_numpy(g.uniform(0, 1, (2, 3, 128, 128)).astype(np.float32)).cuda()
+    gen = PM.PaperGenerator(D, R, K, Ds, params=pg.flatten(P, D, R, K, Ds).astype(np.float32))
+    o = gen.forward(x)
+    up = {k: torch.from_numpy(g.normal(0, 1, tuple(v.shape)).astype(np.float32)).cuda() for k, v in o.items()}
+    full = host(gen.backward(up)).copy()
+    part = host(gen.backward({k: up[k] for k in ("U", "s", "V", "lut_w", "lut_b")}))
+    names = [n for n, _ in pg.param_shapes(D, R, K, Ds)]
+    got = pg.unflatten(part, D, R, K, Ds)
+    for n in names:
+        if n.startswith(("s.", "sw.")):
+            assert np.all(got[n] == 0), n
+    assert np.abs(pg.unflatten(full, D, R, K, Ds)["sw.fc2.w"]).max() > 0
+
+
+def test_paper_generator_fp16_input_matches_fp32(PM):
+    g = np.random.default_rng(5)
+    x = g.uniform(0, 1, (1, 3, 512, 384)).astype(np.float16)
+    gen = PM.PaperGenerator(seed=3)
+    a = gen.forward(torch.from_numpy(x).cuda())
+    b = gen.forward(torch.from_numpy(x.astype(np.float32)).cuda())
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+
+
+@pytest.mark.parametrize("K,shape", [(6, (2, 96, 130)), (0, (1, 67, 45))])
+def test_paper_model_transform_matches_oracle(PM, K, shape):
+    """enhance = generator outputs fed to the fused transform with a 1x1 map and a bias:
+    the image must equal the oracle transform of those same outputs."""
+    say(f"paper model transform K={K} shape={shape}")
+    B, H, W = shape
+    P = rand_params(400 + K, K)
+    g = np.random.default_rng(401)
+    x = g.uniform(-0.02, 1.02, (B, 3, H, W)).astype(np.float32)
+    gen = PM.PaperGenerator(D, R, K, Ds, params=pg.flatten(P, D, R, K, Ds).astype(np.float32))
+    xt = torch.from_numpy(x).cuda()
+    o = gen.forward(xt)
+    y = host(gen.transform(xt, o))
+    h = {k: host(v) for k, v in o.items()}
+    if K:
+        ref = ogr.apply_grid(x, h["U"], h["s"], h["V"], h["lut_w"], h["grids"], h["gw"], h["gb"], bias=h["lut_b"])
+    else:
+        from oracle import lut as ol
+        ref = ol.apply(x, h["U"], h["s"], h["V"], h["lut_w"], h["lut_b"])
+    assert np.abs(y - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
+
+
+# ------------------------------------------------------------------ training
+def psnr(y, t):
+    mse = torch.mean((y.float() - t.float()) ** 2).item()
+    return 10 * math.log10(1.0 / mse)
+
+
+def test_paper_model_training_gain(PM, pair_data):
+    """The paper's model trained with dropout on the synthetic pairs (MSE, Adam 1e-4) must
+    beat doing nothing on held-out pairs."""
+    xtr, ttr, xte, tte = pair_data
+    steps, batch = 2000, 16
+    gen = PM.PaperGenerator(seed=0)
+    tr = PM.PaperTrainer(gen, lr=1e-4)
+    g = np.random.default_rng(0)
+    t0 = time.time()
+    for it in range(steps):
+        idx = torch.from_numpy(g.integers(0, xtr.shape[0], batch)).cuda()
+        tr.step(xtr.index_select(0, idx).contiguous(), ttr.index_select(0, idx).contiguous())
+    torch.cuda.synchronize()
+    t1 = time.time()
+    ys = [gen.enhance(xte[i:i + 16].contiguous()) for i in range(0, xte.shape[0], 16)]
+    p_model = psnr(torch.cat(ys), tte)
+    p_id = psnr(xte, tte)
+    say(f"paper model held-out PSNR: identity {p_id:.2f} dB, trained {p_model:.2f} dB "
+        f"({steps} steps x {batch}, {t1 - t0:.1f}s)")
+    assert np.isfinite(p_model)
+    assert p_model >= p_id + 0.5
