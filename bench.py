@@ -409,8 +409,12 @@ def row_p1(svd, torch, synth, args):
         o = box["o"]
         ms_tr = event_time(lambda i: svd.apply_grid(x, o["U"], o["s"], o["V"], o["lut_w"], o["grids"], o["gw"],
                                                     o["gb"], bias=o["lut_b"], out=y), steps, 3, torch)
+        enh = PM.PaperEnhancer(gen, B, 2160, 3840)
+        ms_graph = event_time(lambda i: enh.graph.replay(), steps, 3, torch)
         res[f"b{B}"] = {"ms": round(ms, 4), "generator_ms": round(ms_gen, 4), "transform_ms": round(ms_tr, 4),
-                        "mpix_s": round(B * 3840 * 2160 / (ms * 1e-3) / 1e6, 1)}
+                        "mpix_s": round(B * 3840 * 2160 / (ms * 1e-3) / 1e6, 1), "graph_ms": round(ms_graph, 4),
+                        "graph_mpix_s": round(B * 3840 * 2160 / (ms_graph * 1e-3) / 1e6, 1)}
+        del enh
     xb = torch.rand(16, 3, 256, 256, device="cuda")
     tb = torch.rand(16, 3, 256, 256, device="cuda")
     tr = PM.PaperTrainer(PM.PaperGenerator(33, 8, 6, 17, seed=1), lr=1e-4)

@@ -246,13 +246,26 @@ __global__ void __launch_bounds__(256) mfma_gemm_kernel(AL al, BL bl, EP ep, int
 #pragma unroll
     for (int t = 0; t < NT; ++t) bc[t] = bl.col(n0 + 16 * t + (lane & 15));
     const int kl = 4 * (lane >> 4);
-    for (int k = kb; k < ke; k += 16) {
-        const bf16x4 a = al.load(ar, k + kl);
+    // operands of step k + 16 are gathered while the matrix cores work on step k
+    bf16x4 a = al.load(ar, kb + kl);
+    bf16x4 b[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) {
-            const bf16x4 b = bl.load(bc[t], k + kl);
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+    for (int t = 0; t < NT; ++t) b[t] = bl.load(bc[t], kb + kl);
+    for (int k = kb; k < ke; k += 16) {
+        bf16x4 an = {0, 0, 0, 0};
+        bf16x4 bn[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) bn[t] = bf16x4{0, 0, 0, 0};
+        if (k + 16 < ke) {
+            an = al.load(ar, k + 16 + kl);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) bn[t] = bl.load(bc[t], k + 16 + kl);
         }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[t], 0, 0, 0);
+        a = an;
+#pragma unroll
+        for (int t = 0; t < NT; ++t) b[t] = bn[t];
     }
 #pragma unroll
     for (int t = 0; t < NT; ++t)
@@ -260,12 +273,22 @@ __global__ void __launch_bounds__(256) mfma_gemm_kernel(AL al, BL bl, EP ep, int
         for (int i = 0; i < 4; ++i) ep(m0 + 4 * (lane >> 4) + i, n0 + 16 * t + (lane & 15), acc[t][i]);
 }
 
+// k range per workgroup and number of k slices for a requested split of a K-long reduction
+inline int gemm_kchunk(int K, int splitk) {
+    const int Kp = (K + 15) / 16 * 16;
+    return ((Kp + splitk - 1) / splitk + 15) / 16 * 16;
+}
+inline int gemm_slices(int K, int splitk) {
+    const int Kp = (K + 15) / 16 * 16;
+    const int kc = gemm_kchunk(K, splitk);
+    return (Kp + kc - 1) / kc;
+}
+
 template <int NT, class AL, class BL, class EP>
 void gemm(AL al, BL bl, EP ep, int M, int N, int K, int splitk, hipStream_t st) {
     const int Kp = (K + 15) / 16 * 16;
-    int kchunk = (Kp + splitk - 1) / splitk;
-    kchunk = (kchunk + 15) / 16 * 16;
-    const int gz = (Kp + kchunk - 1) / kchunk;
+    const int kchunk = gemm_kchunk(K, splitk);
+    const int gz = gemm_slices(K, splitk);
     dim3 grid((M + 63) / 64, (N + 16 * NT - 1) / (16 * NT), gz);
     hipLaunchKernelGGL((mfma_gemm_kernel<NT, AL, BL, EP>), grid, dim3(256), 0, st, al, bl, ep, Kp, kchunk);
 }

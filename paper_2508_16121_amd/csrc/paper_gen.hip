@@ -25,7 +25,6 @@ constexpr int kFeat = 256;           // 8m channels x 2 x 2 pooled
 constexpr float kSlope = 0.2f;
 constexpr float kEps = 1e-5f;
 constexpr int kHeads = 4;            // t, tw, s, sw
-constexpr int kNormThreads = 1024;
 
 int blk_hw(int j) { return kNet >> j; }            // spatial size of activation j (0..5)
 int blk_cs(int j) { return j == 0 ? 4 : kPCh[j]; } // channel stride of the bf16 activation j
@@ -73,93 +72,201 @@ struct DzArr {                   // precomputed dL/dz, fp32 NHWC [M][C]
 };
 
 // ---------------------------------------------------------------- instance norm
-// One workgroup of 1024 threads per image; thread t owns channel t % C and every
-// (1024 / C)-th pixel from t / C, so each pass reads the NHWC block coalesced.  Partial
-// sums are combined by a fixed-order tree over the pixel lanes of each channel.
-__device__ void channel_tree(float* red, int t, int C) {
-    for (int s = kNormThreads / 2; s >= C; s >>= 1) {
+// Each image's H x W pixels are cut into chunks of 4096 / C pixels (16 values per thread);
+// one workgroup of kNormThreads threads per (image, chunk).  Thread t owns channel t % C and
+// every (kNormThreads / C)-th pixel of the chunk from t / C, so each pass reads the NHWC block
+// coalesced.  The statistics kernel writes each chunk's per-channel sums; the kernel that
+// applies the norm (or its gradient) merges the chunks of its image with a fixed-order tree,
+// so the result does not depend on scheduling.  Every layer has exactly 256 chunk x channel
+// partials per image (chunks = HW C / 4096).  Forward sums (x and x^2) are accumulated in
+// fp64 so the variance E[x^2] - mean^2 does not cancel.
+constexpr int kNormThreads = 256;
+constexpr int kNormPer = 16;                       // values per thread per chunk
+
+__host__ __device__ inline int norm_chunk_px(int C) { return kNormThreads * kNormPer / C; }
+__host__ __device__ inline int norm_chunks(int HW, int C) { return (HW + norm_chunk_px(C) - 1) / norm_chunk_px(C); }
+
+template <typename T>
+__device__ void pair_tree(T* r0, T* r1, int t, int stop) {
+    for (int s = kNormThreads / 2; s >= stop; s >>= 1) {
         __syncthreads();
-        if (t < s) red[t] += red[t + s];
+        if (t < s) {
+            r0[t] += r0[t + s];
+            r1[t] += r1[t + s];
+        }
     }
     __syncthreads();
 }
 
-__global__ void __launch_bounds__(kNormThreads) norm_fwd_kernel(const float* __restrict__ h, uint16_t* __restrict__ a,
-                                                                  float* __restrict__ mu, float* __restrict__ rs,
-                                                                  const float* __restrict__ gamma,
-                                                                  const float* __restrict__ beta, int HW, int C) {
-    __shared__ float red[kNormThreads];
+// Merge the nch x C partials of image b into per-channel totals: thread t takes partial
+// index t (chunk t / C, channel t % C) and a tree over the chunks leaves channel c's totals
+// in slot c.  nch * C <= kNormThreads.
+template <typename T, typename P>
+__device__ void merge_partials(const P* part, int b, int nch, int C, T* r0, T* r1) {
+    const int t = threadIdx.x;
+    T v0 = 0, v1 = 0;
+    if (t < nch * C) {
+        const P v = part[static_cast<int64_t>(b) * nch * C + t];
+        v0 = v.x;
+        v1 = v.y;
+    }
+    r0[t] = v0;
+    r1[t] = v1;
+    pair_tree(r0, r1, t, C);
+}
+
+// part[(b * nch + chunk) * C + c] = (sum x, sum x^2) over the chunk, fp64
+__global__ void __launch_bounds__(kNormThreads) norm_stats_kernel(const float* __restrict__ h,
+                                                                    double2* __restrict__ part, int HW, int C) {
+    __shared__ double r0[kNormThreads], r1[kNormThreads];
+    const int nch = norm_chunks(HW, C), cpx = norm_chunk_px(C);
+    const int b = blockIdx.x / nch, ch = blockIdx.x - b * nch;
+    const int p0 = ch * cpx, p1 = min(HW, p0 + cpx);
     const int t = threadIdx.x, c = t % C, pstep = kNormThreads / C;
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * HW * C;
-    float acc = 0.f;
-    for (int p = t / C; p < HW; p += pstep) acc += h[base + static_cast<int64_t>(p) * C + c];
-    red[t] = acc;
-    channel_tree(red, t, C);
-    const float mean = red[c] / static_cast<float>(HW);
-    __syncthreads();
-    acc = 0.f;
-    for (int p = t / C; p < HW; p += pstep) {
-        const float d = h[base + static_cast<int64_t>(p) * C + c] - mean;
-        acc = fmaf(d, d, acc);
+    const float* hb = h + static_cast<int64_t>(b) * HW * C;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll 4
+    for (int p = p0 + t / C; p < p1; p += pstep) {
+        const double v = hb[static_cast<int64_t>(p) * C + c];
+        s0 += v;
+        s1 = fma(v, v, s1);
     }
-    red[t] = acc;
-    channel_tree(red, t, C);
-    const float rstd = 1.f / sqrtf(red[c] / static_cast<float>(HW) + kEps);
+    r0[t] = s0;
+    r1[t] = s1;
+    pair_tree(r0, r1, t, C);
+    if (t < C) part[static_cast<int64_t>(blockIdx.x) * C + c] = make_double2(r0[c], r1[c]);
+}
+
+// a = bf16(scale * (h - mean) * rstd + shift) over this workgroup's chunk; chunk 0 of each
+// image also stores the image's mean and rstd for the backward.
+__global__ void __launch_bounds__(kNormThreads) norm_apply_kernel(const float* __restrict__ h,
+                                                                    const double2* __restrict__ part,
+                                                                    uint16_t* __restrict__ a, float* __restrict__ mu,
+                                                                    float* __restrict__ rs,
+                                                                    const float* __restrict__ gamma,
+                                                                    const float* __restrict__ beta, int HW, int C) {
+    __shared__ double r0[kNormThreads], r1[kNormThreads];
+    __shared__ float coef[2][64];
+    const int nch = norm_chunks(HW, C), cpx = norm_chunk_px(C);
+    const int b = blockIdx.x / nch, ch = blockIdx.x - b * nch;
+    const int t = threadIdx.x;
+    merge_partials(part, b, nch, C, r0, r1);
     if (t < C) {
-        mu[blockIdx.x * C + c] = mean;
-        rs[blockIdx.x * C + c] = rstd;
+        const double m = r0[t] / HW;
+        const double var = fmax(r1[t] / HW - m * m, 0.0);
+        const float mean = static_cast<float>(m);
+        const float rstd = 1.f / sqrtf(static_cast<float>(var) + kEps);
+        if (ch == 0) {
+            mu[b * C + t] = mean;
+            rs[b * C + t] = rstd;
+        }
+        const float g = gamma[t] * rstd;
+        coef[0][t] = g;
+        coef[1][t] = beta[t] - g * mean;
     }
-    const float g = gamma[c] * rstd, sh = beta[c] - g * mean;
-    for (int p = t / C; p < HW; p += pstep) {
+    __syncthreads();
+    const int p0 = ch * cpx, p1 = min(HW, p0 + cpx);
+    const int c = t % C, pstep = kNormThreads / C;
+    const float g = coef[0][c], sh = coef[1][c];
+    const int64_t base = static_cast<int64_t>(b) * HW * C;
+#pragma unroll 4
+    for (int p = p0 + t / C; p < p1; p += pstep) {
         const int64_t o = base + static_cast<int64_t>(p) * C + c;
         a[o] = f2bf(fmaf(g, h[o], sh));
     }
 }
 
-// da = dL/d(norm output); writes dz = dL/d(conv output before LeakyReLU) and adds the scale
-// and shift gradients of this image.
-__global__ void __launch_bounds__(kNormThreads) norm_bwd_kernel(const float* __restrict__ h, const float* __restrict__ da,
-                                                                  const float* __restrict__ mu,
-                                                                  const float* __restrict__ rs,
-                                                                  const float* __restrict__ gamma,
-                                                                  float* __restrict__ dgamma, float* __restrict__ dbeta,
-                                                                  float* __restrict__ dz, int HW, int C) {
-    __shared__ float red[2][kNormThreads];
+// Backward statistics: per chunk, sum of da and sum of da * xhat (xhat from the image's
+// forward mean and rstd), fp32.
+__global__ void __launch_bounds__(kNormThreads) norm_bwd_stats_kernel(const float* __restrict__ h,
+                                                                        const float* __restrict__ da,
+                                                                        const float* __restrict__ mu,
+                                                                        const float* __restrict__ rs,
+                                                                        float2* __restrict__ part, int HW, int C) {
+    __shared__ float r0[kNormThreads], r1[kNormThreads];
+    const int nch = norm_chunks(HW, C), cpx = norm_chunk_px(C);
+    const int b = blockIdx.x / nch, ch = blockIdx.x - b * nch;
+    const int p0 = ch * cpx, p1 = min(HW, p0 + cpx);
     const int t = threadIdx.x, c = t % C, pstep = kNormThreads / C;
-    const int64_t base = static_cast<int64_t>(blockIdx.x) * HW * C;
-    const float mean = mu[blockIdx.x * C + c], rstd = rs[blockIdx.x * C + c];
+    const float mean = mu[b * C + c], rstd = rs[b * C + c];
+    const int64_t base = static_cast<int64_t>(b) * HW * C;
     float s0 = 0.f, s1 = 0.f;
-    for (int p = t / C; p < HW; p += pstep) {
+#pragma unroll 4
+    for (int p = p0 + t / C; p < p1; p += pstep) {
         const int64_t o = base + static_cast<int64_t>(p) * C + c;
         const float g = da[o];
         s0 += g;
         s1 = fmaf(g, (h[o] - mean) * rstd, s1);
     }
-    red[0][t] = s0;
-    red[1][t] = s1;
-    for (int s = kNormThreads / 2; s >= C; s >>= 1) {
-        __syncthreads();
-        if (t < s) {
-            red[0][t] += red[0][t + s];
-            red[1][t] += red[1][t + s];
+    r0[t] = s0;
+    r1[t] = s1;
+    pair_tree(r0, r1, t, C);
+    if (t < C) part[static_cast<int64_t>(blockIdx.x) * C + c] = make_float2(r0[c], r1[c]);
+}
+
+// dz = dL/d(conv output before LeakyReLU) over this chunk; chunk 0 of each image adds the
+// image's scale and shift gradients.
+__global__ void __launch_bounds__(kNormThreads) norm_bwd_apply_kernel(const float* __restrict__ h,
+                                                                        const float* __restrict__ da,
+                                                                        const float2* __restrict__ part,
+                                                                        const float* __restrict__ mu,
+                                                                        const float* __restrict__ rs,
+                                                                        const float* __restrict__ gamma,
+                                                                        float* __restrict__ dgamma,
+                                                                        float* __restrict__ dbeta,
+                                                                        float* __restrict__ dz, int HW, int C) {
+    __shared__ float r0[kNormThreads], r1[kNormThreads];
+    __shared__ float coef[2][64];
+    const int nch = norm_chunks(HW, C), cpx = norm_chunk_px(C);
+    const int b = blockIdx.x / nch, ch = blockIdx.x - b * nch;
+    const int t = threadIdx.x;
+    merge_partials(part, b, nch, C, r0, r1);
+    if (t < C) {
+        const float s0 = r0[t], s1 = r1[t];
+        if (ch == 0) {
+            __hip_atomic_fetch_add(dbeta + t, s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_fetch_add(dgamma + t, s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
+        const float inv = 1.f / static_cast<float>(HW);
+        coef[0][t] = gamma[t] * s0 * inv;
+        coef[1][t] = gamma[t] * s1 * inv;
     }
     __syncthreads();
-    const float sum_da = red[0][c], sum_dax = red[1][c];
-    if (t < C) {
-        __hip_atomic_fetch_add(dbeta + c, sum_da, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_fetch_add(dgamma + c, sum_dax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    const float gm = gamma[c];
-    const float inv = 1.f / static_cast<float>(HW);
-    const float m1 = gm * sum_da * inv, m2 = gm * sum_dax * inv;
-    for (int p = t / C; p < HW; p += pstep) {
+    const int p0 = ch * cpx, p1 = min(HW, p0 + cpx);
+    const int c = t % C, pstep = kNormThreads / C;
+    const float m1 = coef[0][c], m2 = coef[1][c];
+    const float mean = mu[b * C + c], rstd = rs[b * C + c], gm = gamma[c];
+    const int64_t base = static_cast<int64_t>(b) * HW * C;
+#pragma unroll 4
+    for (int p = p0 + t / C; p < p1; p += pstep) {
         const int64_t o = base + static_cast<int64_t>(p) * C + c;
         const float hv = h[o];
         const float xh = (hv - mean) * rstd;
         const float d = rstd * (gm * da[o] - m1 - xh * m2);
         dz[o] = hv > 0.f ? d : kSlope * d;
     }
+}
+
+// ---------------------------------------------------------------- split-K forward convolution
+// Small layers (few output pixels) split the 9 Cin reduction over workgroups: each writes its
+// partial product to part[z][m][n]; the sum over z in fixed order, the bias and the LeakyReLU
+// follow in a second kernel.
+struct EpiPartial {
+    float* part;
+    int M, N;
+    __device__ void operator()(int m, int n, float v) const {
+        if (m < M && n < N) part[(static_cast<int64_t>(blockIdx.z) * M + m) * N + n] = v;
+    }
+};
+
+__global__ void splitk_lrelu_kernel(const float* __restrict__ part, int splits, const float* __restrict__ bias,
+                                    float* __restrict__ out, int M, int N) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t MN = static_cast<int64_t>(M) * N;
+    if (i >= MN) return;
+    float z = bias[static_cast<int>(i % N)];
+    for (int k = 0; k < splits; ++k) z += part[k * MN + i];
+    out[i] = z > 0.f ? z : kSlope * z;
 }
 
 // ---------------------------------------------------------------- dropout + pooling
@@ -408,7 +515,33 @@ struct PWS {
     float* df;                   // [B][256]
     float* dz[kBlocks];          // dL/d(conv output) of blocks 1..5 (index j - 1)
     float* da[kBlocks];          // dL/d(bf16 activation j), j = 1..4
+    double2* part;               // per-chunk norm statistics [B][chunks x C = 256]
+    float* skp;                  // split-K partial products of the small forward convolutions
 };
+
+ConvGeo pconv_geo(int i, int B) {      // block i (0..4): activation i -> LeakyReLU output i + 1
+    ConvGeo g;
+    g.N = B;
+    g.Hi = g.Wi = blk_hw(i);
+    g.Ci = kPCh[i];
+    g.Cs = blk_cs(i);
+    g.Ho = g.Wo = blk_hw(i + 1);
+    g.Co = kPCh[i + 1];
+    g.Cos = kPCh[i + 1];
+    g.stride = 2;
+    return g;
+}
+
+// Workgroups of a forward convolution are too few to hide the operand gathers when the layer
+// has few output pixels: split its reduction so that about 256 workgroups run (at least two
+// k steps each).
+int fwd_splits(const ConvGeo& g) {
+    const int M = g.N * g.Ho * g.Wo;
+    const int ksteps = (9 * g.Cs + 15) / 16;
+    const int wgs = ((M + 63) / 64) * ((g.Co + 15) / 16);
+    if (wgs >= 128) return 1;
+    return std::max(1, std::min(ksteps / 2, (256 + wgs - 1) / wgs));
+}
 
 size_t carve_pws(char* base, int B, int total, PWS* w) {
     size_t off = 0;
@@ -430,20 +563,16 @@ size_t carve_pws(char* base, int B, int total, PWS* w) {
     w->dO = reinterpret_cast<float*>(take(4 * static_cast<size_t>(B) * total));
     w->dhid = reinterpret_cast<float*>(take(4 * static_cast<size_t>(B) * kHeads * kHid));
     w->df = reinterpret_cast<float*>(take(4 * static_cast<size_t>(B) * kFeat));
+    w->part = reinterpret_cast<double2*>(take(sizeof(double2) * static_cast<size_t>(B) * kNormThreads));
+    size_t nsk = 0;
+    for (int i = 0; i < kBlocks; ++i) {
+        const ConvGeo g = pconv_geo(i, B);
+        const int sk = fwd_splits(g);
+        if (sk > 1)
+            nsk = std::max<size_t>(nsk, static_cast<size_t>(gemm_slices(9 * g.Cs, sk)) * g.N * g.Ho * g.Wo * g.Co);
+    }
+    w->skp = reinterpret_cast<float*>(take(sizeof(float) * nsk));
     return off;
-}
-
-ConvGeo pconv_geo(int i, int B) {      // block i (0..4): activation i -> LeakyReLU output i + 1
-    ConvGeo g;
-    g.N = B;
-    g.Hi = g.Wi = blk_hw(i);
-    g.Ci = kPCh[i];
-    g.Cs = blk_cs(i);
-    g.Ho = g.Wo = blk_hw(i + 1);
-    g.Co = kPCh[i + 1];
-    g.Cos = kPCh[i + 1];
-    g.stride = 2;
-    return g;
 }
 
 int grid1d(int64_t n, int t = 256) { return static_cast<int>((n + t - 1) / t); }
@@ -482,10 +611,21 @@ svdlut_status paper_generator_forward(const float* params, const void* x, svdlut
     for (int i = 0; i < kBlocks; ++i) {
         const ConvGeo g = pconv_geo(i, B);
         const int M = B * g.Ho * g.Wo;
-        gemm_nt(g.Co, FwdA{k.a[i], g}, FwdB{P.cw[i], g}, EpiLrelu{k.h[i], P.cb[i], M, g.Co}, M, 9 * g.Cs, 1, st);
-        if (i < kBlocks - 1)
-            hipLaunchKernelGGL(norm_fwd_kernel, dim3(B), dim3(kNormThreads), 0, st, k.h[i], k.a[i + 1], k.mu[i],
-                               k.rs[i], P.ng[i], P.nb[i], g.Ho * g.Wo, g.Co);
+        const int sk = fwd_splits(g);
+        if (sk > 1) {
+            gemm<1>(FwdA{k.a[i], g}, FwdB{P.cw[i], g}, EpiPartial{k.skp, M, g.Co}, M, g.Co, 9 * g.Cs, sk, st);
+            hipLaunchKernelGGL(splitk_lrelu_kernel, dim3(grid1d(static_cast<int64_t>(M) * g.Co)), dim3(256), 0, st,
+                               k.skp, gemm_slices(9 * g.Cs, sk), P.cb[i], k.h[i], M, g.Co);
+        } else {
+            gemm_nt(g.Co, FwdA{k.a[i], g}, FwdB{P.cw[i], g}, EpiLrelu{k.h[i], P.cb[i], M, g.Co}, M, 9 * g.Cs, 1, st);
+        }
+        if (i < kBlocks - 1) {
+            const int HW = g.Ho * g.Wo;
+            const dim3 grid(B * norm_chunks(HW, g.Co));
+            hipLaunchKernelGGL(norm_stats_kernel, grid, dim3(kNormThreads), 0, st, k.h[i], k.part, HW, g.Co);
+            hipLaunchKernelGGL(norm_apply_kernel, grid, dim3(kNormThreads), 0, st, k.h[i], k.part, k.a[i + 1], k.mu[i],
+                               k.rs[i], P.ng[i], P.nb[i], HW, g.Co);
+        }
     }
     hipLaunchKernelGGL(pool_fwd_kernel, dim3(grid1d(B * kFeat)), dim3(256), 0, st, k.h[kBlocks - 1], mask, k.f, B);
     hipLaunchKernelGGL(hid_fwd_kernel, dim3(grid1d(B * hs.n * kHid)), dim3(256), 0, st, k.f, hs, k.hid, B);
@@ -533,8 +673,12 @@ svdlut_status paper_generator_backward(const float* params, const uint8_t* mask,
         if (i == 0) break;
         // norm of block i (its output is activation i): da[i - 1] -> dz[i - 1]
         const int HW = blk_hw(i) * blk_hw(i), C = kPCh[i];
-        hipLaunchKernelGGL(norm_bwd_kernel, dim3(B), dim3(kNormThreads), 0, st, k.h[i - 1], k.da[i - 1], k.mu[i - 1],
-                           k.rs[i - 1], P.ng[i - 1], G.ng[i - 1], G.nb[i - 1], k.dz[i - 1], HW, C);
+        const dim3 grid(B * norm_chunks(HW, C));
+        float2* bpart = reinterpret_cast<float2*>(k.part);
+        hipLaunchKernelGGL(norm_bwd_stats_kernel, grid, dim3(kNormThreads), 0, st, k.h[i - 1], k.da[i - 1],
+                           k.mu[i - 1], k.rs[i - 1], bpart, HW, C);
+        hipLaunchKernelGGL(norm_bwd_apply_kernel, grid, dim3(kNormThreads), 0, st, k.h[i - 1], k.da[i - 1], bpart,
+                           k.mu[i - 1], k.rs[i - 1], P.ng[i - 1], G.ng[i - 1], G.nb[i - 1], k.dz[i - 1], HW, C);
     }
     return check_launch("paper_generator_bwd");
 }

@@ -180,6 +180,23 @@ def test_paper_model_transform_matches_oracle(PM, K, shape):
     assert np.abs(y - ref).max() <= 1e-5 * max(1.0, np.abs(ref).max())
 
 
+def test_paper_enhancer_graph_replays_match_eager(PM):
+    """The graph-captured inference equals the eager path bit for bit on every replay, with
+    eager work and synchronisations between the replays."""
+    g = np.random.default_rng(501)
+    gen = PM.PaperGenerator(D, R, 6, Ds, params=pg.flatten(rand_params(500, 6), D, R, 6, Ds).astype(np.float32))
+    xs = [torch.from_numpy(g.uniform(0, 1, (2, 3, 180, 260)).astype(np.float32)).cuda() for _ in range(3)]
+    eager = [gen.enhance(x).clone() for x in xs]
+    enh = PM.PaperEnhancer(gen, 2, 180, 260)
+    for rep in range(2):
+        for i in (0, 2, 1):
+            y = enh(xs[i]).clone()
+            torch.cuda.synchronize()
+            assert torch.equal(y, eager[i]), (rep, i)
+            gen.enhance(xs[(i + 1) % 3])          # eager work between replays
+            torch.cuda.synchronize()
+
+
 # ------------------------------------------------------------------ training
 def psnr(y, t):
     mse = torch.mean((y.float() - t.float()) ** 2).item()
