@@ -62,6 +62,23 @@ struct EpiAct {          // bf16(relu(acc + bias)) into NHWC, channel stride Cos
         if (m < M && co < Cos) out[static_cast<int64_t>(m) * Cos + co] = co < Co ? f2bf(fmaxf(v + bias[co], 0.f)) : 0;
     }
 };
+// sum of the split-K slices in fixed order + bias -> ReLU -> bf16 NHWC (channel stride Cos,
+// padding channels zero)
+__global__ void splitk_relu_kernel(const float* __restrict__ part, int splits, const float* __restrict__ bias,
+                                   uint16_t* __restrict__ out, int M, int Co, int Cos) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t MN = static_cast<int64_t>(M) * Cos;
+    if (i >= MN) return;
+    const int co = static_cast<int>(i % Cos);
+    if (co >= Co) {
+        out[i] = 0;
+        return;
+    }
+    float z = bias[co];
+    for (int k = 0; k < splits; ++k) z += part[k * MN + i];
+    out[i] = f2bf(fmaxf(z, 0.f));
+}
+
 struct EpiMap {          // acc + bias into the planar [n][9][32][32] map (linear head)
     float* out;
     const float* bias;
@@ -131,13 +148,26 @@ __global__ void fc_wgrad_kernel(const float* __restrict__ dout, const float* __r
     else db[j] = acc;
 }
 
-// dg[n][c] = sum_j dout[n][j] W[j][c]: one workgroup per n, one thread per c.
+// dg[n][c] = sum_j dout[n][j] W[j][c].  The j range is cut into chunks of kDgChunk rows, one
+// workgroup (one thread per c) per (n, chunk), partial sums to part[n][chunk][c]; a second
+// kernel adds the chunks in order.
+constexpr int kDgChunk = 64;
+
 __global__ void fc_dgrad_kernel(const float* __restrict__ dout, const float* __restrict__ Wt,
-                                float* __restrict__ dg, int nout) {
-    const int n = blockIdx.x, c = threadIdx.x;
+                                float* __restrict__ part, int nout) {
+    const int n = blockIdx.x, ch = blockIdx.y, c = threadIdx.x;
+    const int j0 = ch * kDgChunk, j1 = min(nout, j0 + kDgChunk);
     const float* d = dout + static_cast<int64_t>(n) * nout;
     float acc = 0.f;
-    for (int j = 0; j < nout; ++j) acc = fmaf(d[j], Wt[static_cast<int64_t>(j) * kGap + c], acc);
+#pragma unroll 8
+    for (int j = j0; j < j1; ++j) acc = fmaf(d[j], Wt[static_cast<int64_t>(j) * kGap + c], acc);
+    part[(static_cast<int64_t>(n) * gridDim.y + ch) * kGap + c] = acc;
+}
+
+__global__ void fc_dgrad_reduce_kernel(const float* __restrict__ part, float* __restrict__ dg, int nch) {
+    const int n = blockIdx.x, c = threadIdx.x;
+    float acc = 0.f;
+    for (int k = 0; k < nch; ++k) acc += part[(static_cast<int64_t>(n) * nch + k) * kGap + c];
     dg[n * kGap + c] = acc;
 }
 
@@ -170,15 +200,36 @@ int act_c(int i) { return i == 0 ? 4 : kCh[i]; }      // channel stride of activ
 int act_hw(int i) { return kNet >> i; }
 
 struct WS {
+    float* skp;                  // split-K partial products of the small forward convolutions
+    float* wpart;                // split-K partial products of the weight gradients
     uint16_t* a[kConvs + 1];     // activations a0..a5 (bf16 NHWC)
     float* g;                    // [B][128]
     float* dout;                 // [B][nfc]
     float* dg;                   // [B][128]
+    float* dgp;                  // [B][chunks][128] partial sums of dg
     float* da[kConvs];           // da[i] = gradient w.r.t. activation i (i = 1..4), fp32 NHWC
 };
 
+ConvGeo conv_geo(int i, int B);
+ConvGeo head_geo(int B);
+
+int fwd_splits(const ConvGeo& g) { return fwd_splits(g.N * g.Ho * g.Wo, g.Cos, 9 * g.Cs); }
+
 size_t carve_ws(char* base, int B, int D, int R, WS* w) {
     size_t off = 0;
+    size_t nsk = 0;
+    for (int i = 0; i < kConvs; ++i) {
+        const ConvGeo g = conv_geo(i, B);
+        const int sk = fwd_splits(g);
+        if (sk > 1)
+            nsk = std::max<size_t>(nsk, static_cast<size_t>(gemm_slices(9 * g.Cs, sk)) * g.N * g.Ho * g.Wo * g.Cos);
+    }
+    if (w) w->skp = reinterpret_cast<float*>(base + off);
+    off = align256(off + sizeof(float) * nsk);
+    size_t nwp = wgrad_part_floats(head_geo(B));
+    for (int i = 0; i < kConvs; ++i) nwp = std::max(nwp, wgrad_part_floats(conv_geo(i, B)));
+    if (w) w->wpart = reinterpret_cast<float*>(base + off);
+    off = align256(off + sizeof(float) * nwp);
     for (int i = 0; i <= kConvs; ++i) {
         const size_t n = static_cast<size_t>(B) * act_hw(i) * act_hw(i) * act_c(i);
         if (w) w->a[i] = reinterpret_cast<uint16_t*>(base + off);
@@ -191,6 +242,8 @@ size_t carve_ws(char* base, int B, int D, int R, WS* w) {
     off = align256(off + sizeof(float) * B * nfc);
     if (w) w->dg = reinterpret_cast<float*>(base + off);
     off = align256(off + sizeof(float) * B * kGap);
+    if (w) w->dgp = reinterpret_cast<float*>(base + off);
+    off = align256(off + sizeof(float) * B * kGap * ((nfc + kDgChunk - 1) / kDgChunk));
     for (int i = 1; i < kConvs; ++i) {
         const size_t n = static_cast<size_t>(B) * act_hw(i) * act_hw(i) * act_c(i);
         if (w) w->da[i] = reinterpret_cast<float*>(base + off);
@@ -255,7 +308,16 @@ svdlut_status generator_forward(const float* params, const void* x, svdlut_dtype
     for (int i = 0; i < kConvs; ++i) {
         const ConvGeo g = conv_geo(i, B);
         const int M = B * g.Ho * g.Wo;
-        gemm_nt(g.Cos, FwdA{k.a[i], g}, FwdB{w[i], g}, EpiAct{k.a[i + 1], b[i], M, g.Co, g.Cos}, M, 9 * g.Cs, 1, st);
+        const int sk = fwd_splits(g);
+        if (sk > 1) {
+            gemm<1>(FwdA{k.a[i], g}, FwdB{w[i], g}, EpiPartial{k.skp, M, g.Cos}, M, g.Cos, 9 * g.Cs, sk, st);
+            const int64_t n = static_cast<int64_t>(M) * g.Cos;
+            hipLaunchKernelGGL(splitk_relu_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                               k.skp, gemm_slices(9 * g.Cs, sk), b[i], k.a[i + 1], M, g.Co, g.Cos);
+        } else {
+            gemm_nt(g.Cos, FwdA{k.a[i], g}, FwdB{w[i], g}, EpiAct{k.a[i + 1], b[i], M, g.Co, g.Cos}, M, 9 * g.Cs, 1,
+                    st);
+        }
         if (i == 2) {
             const ConvGeo hg = head_geo(B);
             const int Mh = B * kMapHW * kMapHW;
@@ -284,24 +346,26 @@ svdlut_status generator_backward(const float* params, const float* dU, const flo
     const int64_t nfw = static_cast<int64_t>(nout) * (kGap + 1);
     hipLaunchKernelGGL(fc_wgrad_kernel, dim3(static_cast<unsigned>((nfw + 255) / 256)), dim3(256), 0, st, k.dout, k.g,
                        gfw, gfb, B, nout);
-    hipLaunchKernelGGL(fc_dgrad_kernel, dim3(B), dim3(kGap), 0, st, k.dout, fw, k.dg, nout);
+    const int nch = (nout + kDgChunk - 1) / kDgChunk;
+    hipLaunchKernelGGL(fc_dgrad_kernel, dim3(B, nch), dim3(kGap), 0, st, k.dout, fw, k.dgp, nout);
+    hipLaunchKernelGGL(fc_dgrad_reduce_kernel, dim3(B), dim3(kGap), 0, st, k.dgp, k.dg, nch);
     // conv5: through the average pool
     {
         const ConvGeo g = conv_geo(4, B);
         DzGap dz{k.dg, k.a[5], kGap, g.Ho * g.Wo, 1.f / static_cast<float>(g.Ho * g.Wo)};
-        conv_backward(g, dz, k.a[4], w[4], gw[4], gb[4], k.da[4], 0, st);
+        conv_backward(g, dz, k.a[4], w[4], gw[4], gb[4], k.da[4], 0, k.wpart, st);
     }
     // conv4 -> gradient of the third activation, then the map head adds its part
     {
         const ConvGeo g = conv_geo(3, B);
-        conv_backward(g, DzMasked{k.da[4], k.a[4], g.Cos}, k.a[3], w[3], gw[3], gb[3], k.da[3], 0, st);
+        conv_backward(g, DzMasked{k.da[4], k.a[4], g.Cos}, k.a[3], w[3], gw[3], gb[3], k.da[3], 0, k.wpart, st);
         const ConvGeo hg = head_geo(B);
-        conv_backward(hg, DzMap{dmap, kMapC, kMapHW * kMapHW}, k.a[3], hw, ghw, ghb, k.da[3], 1, st);
+        conv_backward(hg, DzMap{dmap, kMapC, kMapHW * kMapHW}, k.a[3], hw, ghw, ghb, k.da[3], 1, k.wpart, st);
     }
     for (int i = 2; i >= 0; --i) {
         const ConvGeo g = conv_geo(i, B);
         conv_backward(g, DzMasked{k.da[i + 1], k.a[i + 1], g.Cos}, k.a[i], w[i], gw[i], gb[i],
-                      i > 0 ? k.da[i] : nullptr, 0, st);
+                      i > 0 ? k.da[i] : nullptr, 0, k.wpart, st);
     }
     return check_launch("generator_bwd");
 }

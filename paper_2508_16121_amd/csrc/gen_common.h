@@ -183,8 +183,24 @@ struct WgradB {
     __device__ bf16x4 load(const Col& c, int k) const {
         const int M = g.N * g.Ho * g.Wo;
         bf16x4 v = {0, 0, 0, 0};
-        if (!c.valid) return v;
+        if (!c.valid || k >= M) return v;
         const int ky = c.tap / 3, kx = c.tap - 3 * (c.tap / 3);
+        if ((g.Wo & 3) == 0) {
+            // k is a multiple of 4 and Wo of 4: the four pixels k..k+3 lie in one output row
+            const int HoWo = g.Ho * g.Wo;
+            const int n = k / HoWo;
+            const int p = k - n * HoWo;
+            const int yo = p / g.Wo, xo = p - (p / g.Wo) * g.Wo;
+            const int y = yo * g.stride - 1 + ky;
+            if (y < 0 || y >= g.Hi) return v;
+            const int64_t row = (static_cast<int64_t>(n) * g.Hi + y) * g.Wi;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int x = (xo + j) * g.stride - 1 + kx;
+                if (k + j < M && x >= 0 && x < g.Wi) v[j] = static_cast<short>(in[(row + x) * g.Cs + c.ci]);
+            }
+            return v;
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int m = k + j;
@@ -210,16 +226,6 @@ struct EpiStore {        // plain fp32 store (or accumulate) of an NHWC gradient
             float* p = out + static_cast<int64_t>(m) * C + c;
             *p = accumulate ? *p + v : v;
         }
-    }
-};
-struct EpiWgrad {        // split-K partial of dW[co][tap][ci] (fp32 atomics)
-    float* dw;
-    int Co, Ci, Cs;
-    __device__ void operator()(int co, int n, float v) const {
-        const int tap = n / Cs, ci = n - (n / Cs) * Cs;
-        if (co < Co && tap < 9 && ci < Ci)
-            __hip_atomic_fetch_add(dw + (static_cast<int64_t>(co) * 9 + tap) * Ci + ci, v, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
     }
 };
 
@@ -331,15 +337,48 @@ __global__ void downsample_kernel(const IO* __restrict__ x, uint16_t* __restrict
     }
 }
 
-// Bias gradient: db[co] += sum over a chunk of 64 output pixels of dz(m, co).
+// Bias gradient: db[co] += sum of dz(m, co) over a chunk of output pixels.  256 threads:
+// thread t takes channel t % Co and pixel lane t / Co (256 / Co lanes, 16 pixels each); the
+// lanes of a channel are added in LDS and one atomic per channel and workgroup remains.
+constexpr int kBiasPx = 16;
+
+inline int bias_lanes(int Co) { return std::max(1, 256 / Co); }
+
 template <class DZ>
-__global__ void bias_grad_kernel(DZ dz, float* __restrict__ db, int M, int Co) {
-    const int co = threadIdx.x;
-    if (co >= Co) return;
-    const int m0 = blockIdx.x * 64;
+__global__ void __launch_bounds__(256) bias_grad_kernel(DZ dz, float* __restrict__ db, int M, int Co) {
+    __shared__ float red[256];
+    const int t = threadIdx.x, nl = max(1, 256 / Co);
+    const int co = t % Co, lane = t / Co;
+    const int m0 = blockIdx.x * nl * kBiasPx;
     float acc = 0.f;
-    for (int m = m0; m < min(M, m0 + 64); ++m) acc += dz(m, co);
-    __hip_atomic_fetch_add(db + co, acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (lane < nl && t < Co * nl)
+        for (int m = m0 + lane; m < min(M, m0 + nl * kBiasPx); m += nl) acc += dz(m, co);
+    red[t] = acc;
+    __syncthreads();
+    if (t < Co) {
+        float s = 0.f;
+        for (int l = 0; l < nl; ++l) s += red[l * Co + t];
+        __hip_atomic_fetch_add(db + t, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// dW[co][tap][ci] = sum over the split-K slices of part[z][co][tap * Cs + ci]: one wave per
+// output element, lane l adds slices l, l + 64, ... and a fixed butterfly adds the lanes, so
+// the result does not depend on scheduling.
+__global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restrict__ part, int slices,
+                                                           float* __restrict__ dw, int Co, int Ci, int Cs) {
+    const int N = 9 * Cs;
+    const int i = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (i >= Co * N) return;          // wave-uniform
+    const int64_t stride = static_cast<int64_t>(Co) * N;
+    float acc = 0.f;
+    for (int z = lane; z < slices; z += 64) acc += part[z * stride + i];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    const int co = i / N, n = i - co * N;
+    const int tap = n / Cs, ci = n - tap * Cs;
+    if (lane == 0 && ci < Ci) dw[(static_cast<int64_t>(co) * 9 + tap) * Ci + ci] = acc;
 }
 
 __global__ void zero_f32_kernel(float* p, int64_t n) {
@@ -355,18 +394,58 @@ void gemm_nt(int ncols, AL al, BL bl, EP ep, int M, int K, int splitk, hipStream
     else gemm<4>(al, bl, ep, M, ncols, K, splitk, st);
 }
 
+// Split-K of a forward convolution: workgroups of a layer with few output pixels are too
+// few to hide the operand gathers, so its reduction is split into slices (at least two k
+// steps each) until about 256 workgroups run.  Each slice writes its partial product to
+// part[slice][m][n]; a second kernel sums the slices in fixed order and applies the bias and
+// the activation.  Returns the requested split (1 = no split) for an M x N x K product with
+// 16-column tiles.
+inline int fwd_splits(int M, int N, int K) {
+    const int ksteps = (K + 15) / 16;
+    const int wgs = ((M + 63) / 64) * ((N + 15) / 16);
+    if (wgs >= 128) return 1;
+    return std::max(1, std::min(ksteps / 2, (256 + wgs - 1) / wgs));
+}
+
+struct EpiPartial {
+    float* part;
+    int M, N;
+    __device__ void operator()(int m, int n, float v) const {
+        if (m < M && n < N) part[(static_cast<int64_t>(blockIdx.z) * M + m) * N + n] = v;
+    }
+};
+
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
-int wgrad_split(int M) { return std::max(1, std::min(256, M / 512)); }
+// Weight gradient split: the Co x 9Cs product reduces over all output pixels, so it is split
+// into slices (at least four k steps each) until about 2048 workgroups run; each slice stores
+// its partial product and wgrad_reduce_kernel adds them in fixed order.
+inline int wgrad_splits(const ConvGeo& g) {
+    const int Mo = g.N * g.Ho * g.Wo;
+    const int wgs = ((g.Co + 63) / 64) * ((9 * g.Cs + 63) / 64);
+    const int ksteps = (Mo + 15) / 16;
+    return std::max(1, std::min(ksteps / 4, (2048 + wgs - 1) / wgs));
+}
 
+// floats of split-K partials the weight gradient of layer g needs
+inline size_t wgrad_part_floats(const ConvGeo& g) {
+    const int Mo = g.N * g.Ho * g.Wo;
+    return static_cast<size_t>(gemm_slices(Mo, wgrad_splits(g))) * g.Co * 9 * g.Cs;
+}
+
+// wpart: scratch of at least wgrad_part_floats(g) floats.
 template <class DZ>
 void conv_backward(const ConvGeo& g, DZ dz, const uint16_t* in, const float* w, float* dw, float* db,
-                   float* da_in, int accumulate_da, hipStream_t st) {
+                   float* da_in, int accumulate_da, float* wpart, hipStream_t st) {
     const int Mo = g.N * g.Ho * g.Wo;
-    // weight gradient: [Co] x [9*Cs] over the Mo output pixels (split over workgroups)
-    gemm_nt(9 * g.Cs, WgradA<DZ>{dz, g}, WgradB{in, g}, EpiWgrad{dw, g.Co, g.Ci, g.Cs}, g.Co, Mo,
-            wgrad_split(Mo), st);
-    hipLaunchKernelGGL(bias_grad_kernel<DZ>, dim3((Mo + 63) / 64), dim3(128), 0, st, dz, db, Mo, g.Co);
+    const int N = 9 * g.Cs;
+    const int sk = wgrad_splits(g);
+    gemm<4>(WgradA<DZ>{dz, g}, WgradB{in, g}, EpiPartial{wpart, g.Co, N}, g.Co, N, Mo, sk, st);
+    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((g.Co * N + 3) / 4), dim3(256), 0, st, wpart,
+                       gemm_slices(Mo, sk), dw, g.Co, g.Ci, g.Cs);
+    const int px_per_wg = bias_lanes(g.Co) * kBiasPx;
+    hipLaunchKernelGGL(bias_grad_kernel<DZ>, dim3((Mo + px_per_wg - 1) / px_per_wg), dim3(256), 0, st, dz, db, Mo,
+                       g.Co);
     if (da_in) {
         const int Mi = g.N * g.Hi * g.Wi;
         gemm_nt(g.Ci, DgradA<DZ>{dz, g}, DgradB{w, g}, EpiStore{da_in, Mi, g.Cs, accumulate_da}, Mi,

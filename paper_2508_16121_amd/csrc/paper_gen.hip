@@ -248,17 +248,7 @@ __global__ void __launch_bounds__(kNormThreads) norm_bwd_apply_kernel(const floa
 }
 
 // ---------------------------------------------------------------- split-K forward convolution
-// Small layers (few output pixels) split the 9 Cin reduction over workgroups: each writes its
-// partial product to part[z][m][n]; the sum over z in fixed order, the bias and the LeakyReLU
-// follow in a second kernel.
-struct EpiPartial {
-    float* part;
-    int M, N;
-    __device__ void operator()(int m, int n, float v) const {
-        if (m < M && n < N) part[(static_cast<int64_t>(blockIdx.z) * M + m) * N + n] = v;
-    }
-};
-
+// sum of the split-K slices in fixed order + bias -> LeakyReLU (fp32 NHWC)
 __global__ void splitk_lrelu_kernel(const float* __restrict__ part, int splits, const float* __restrict__ bias,
                                     float* __restrict__ out, int M, int N) {
     const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
@@ -517,6 +507,7 @@ struct PWS {
     float* da[kBlocks];          // dL/d(bf16 activation j), j = 1..4
     double2* part;               // per-chunk norm statistics [B][chunks x C = 256]
     float* skp;                  // split-K partial products of the small forward convolutions
+    float* wpart;                // split-K partial products of the weight gradients
 };
 
 ConvGeo pconv_geo(int i, int B) {      // block i (0..4): activation i -> LeakyReLU output i + 1
@@ -532,16 +523,7 @@ ConvGeo pconv_geo(int i, int B) {      // block i (0..4): activation i -> LeakyR
     return g;
 }
 
-// Workgroups of a forward convolution are too few to hide the operand gathers when the layer
-// has few output pixels: split its reduction so that about 256 workgroups run (at least two
-// k steps each).
-int fwd_splits(const ConvGeo& g) {
-    const int M = g.N * g.Ho * g.Wo;
-    const int ksteps = (9 * g.Cs + 15) / 16;
-    const int wgs = ((M + 63) / 64) * ((g.Co + 15) / 16);
-    if (wgs >= 128) return 1;
-    return std::max(1, std::min(ksteps / 2, (256 + wgs - 1) / wgs));
-}
+int fwd_splits(const ConvGeo& g) { return fwd_splits(g.N * g.Ho * g.Wo, g.Co, 9 * g.Cs); }
 
 size_t carve_pws(char* base, int B, int total, PWS* w) {
     size_t off = 0;
@@ -572,6 +554,9 @@ size_t carve_pws(char* base, int B, int total, PWS* w) {
             nsk = std::max<size_t>(nsk, static_cast<size_t>(gemm_slices(9 * g.Cs, sk)) * g.N * g.Ho * g.Wo * g.Co);
     }
     w->skp = reinterpret_cast<float*>(take(sizeof(float) * nsk));
+    size_t nwp = 0;
+    for (int i = 0; i < kBlocks; ++i) nwp = std::max(nwp, wgrad_part_floats(pconv_geo(i, B)));
+    w->wpart = reinterpret_cast<float*>(take(sizeof(float) * nwp));
     return off;
 }
 
@@ -669,7 +654,7 @@ svdlut_status paper_generator_backward(const float* params, const uint8_t* mask,
     for (int i = kBlocks - 1; i >= 0; --i) {
         const ConvGeo cg = pconv_geo(i, B);
         conv_backward(cg, DzArr{k.dz[i], cg.Co}, k.a[i], P.cw[i], G.cw[i], G.cb[i], i > 0 ? k.da[i - 1] : nullptr, 0,
-                      st);
+                      k.wpart, st);
         if (i == 0) break;
         // norm of block i (its output is activation i): da[i - 1] -> dz[i - 1]
         const int HW = blk_hw(i) * blk_hw(i), C = kPCh[i];
