@@ -1,6 +1,6 @@
 """Benchmark of the 2D-LUT hot path on one MI355X.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows all|none|c1,c3,c4,c5,g1,g4,sweep,u1,p1]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--rows all|none|c1,c3,c4,c5,g1,g4,sweep,dims,u1,p1]
 
 Headline (`value`): svdlut_apply on one 3840x2160 float32 frame (33x33 LUTs at rank 8,
 reconstruction fused, 480x270 spatial map), in Mpix/s, inputs resident in HBM.  Each timed
@@ -31,7 +31,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=10)
-    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1,g4,sweep,u1,p1")
+    ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1,g4,sweep,dims,u1,p1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run device-to-device copies of one 4K fp32 frame (99.5 MB), the reference "
@@ -349,6 +349,37 @@ def row_sweep(svd, torch, synth, args):
     return {"workload": "svdlut_apply 1x3x2160x3840 fp32, map 9x270x480; D x R sweep", "points": out}
 
 
+def row_dims(svd, torch, synth, args):
+    """LUT dimension at the same 4K fp32 frame (D = 33): per-channel 1D LUTs, the 2D
+    decomposition (R = 8) with scalar LUT weights (1x1 map) and with the 9x270x480 spatial map,
+    and a dense 3D LUT.  Four rotating buffer sets, event timing."""
+    g = np.random.default_rng(49)
+    D, R, H, W = 33, 8, 2160, 3840
+    xh = synth.image(g, H, W)[None]
+    bufs = [(torch.from_numpy(xh).cuda(), torch.empty(1, 3, H, W, device="cuda")) for _ in range(N_ROT)]
+    T1 = torch.from_numpy(g.normal(0, 1, (1, 3, D)).astype(np.float32)).cuda()
+    T3 = torch.from_numpy(g.normal(0, 0.3, (1, 3, D, D, D)).astype(np.float32)).cuda()
+    ws3 = torch.empty(svd._lib.load().svdlut_lut3d_workspace_size(1, D) // 4 + 64, device="cuda")
+    U, s, V = (torch.from_numpy(a).cuda() for a in synth.factors(g, 1, D, R))
+    m1 = torch.from_numpy(synth.spatial_map(g, 1, 1, 1)).cuda()
+    mm = torch.from_numpy(synth.spatial_map(g, 1, 270, 480)).cuda()
+    steps = max(10, args.steps // 4)
+    cases = {
+        "lut1d": (lambda i: svd.lut1d_apply(bufs[i % N_ROT][0], T1, out=bufs[i % N_ROT][1]), 3 * D),
+        "lut2d_svd_scalar_weights": (lambda i: svd.apply(bufs[i % N_ROT][0], U, s, V, m1, out=bufs[i % N_ROT][1]),
+                                     9 * (2 * D * R + R) + 9),
+        "lut2d_svd_map": (lambda i: svd.apply(bufs[i % N_ROT][0], U, s, V, mm, out=bufs[i % N_ROT][1]),
+                          9 * (2 * D * R + R)),
+        "lut3d": (lambda i: svd.lut3d_apply(bufs[i % N_ROT][0], T3, out=bufs[i % N_ROT][1], ws=ws3), 3 * D ** 3),
+    }
+    out = {}
+    for k, (fn, npar) in cases.items():
+        ms = event_time(fn, steps, 3, torch)
+        out[k] = {"ms": round(ms, 4), "mpix_s": round(H * W / (ms * 1e-3) / 1e6, 1), "lut_params": npar,
+                  "gb_s_at_24_b_px": round(24 * H * W / (ms * 1e-3) / 1e9, 1)}
+    return {"workload": "1x3x2160x3840 fp32, D=33: 1D LUTs vs 2D SVD (R=8) vs dense 3D LUT", "points": out}
+
+
 def row_c5(svd, torch, synth, args):
     from paper_2508_16121_amd import generator as G
     g = np.random.default_rng(5)
@@ -466,9 +497,9 @@ def main():
         ms_copy = event_time(lambda i: dst.copy_(src), max(5, args.steps // 4), 2, torch)
         out["copy_probe"] = {"bytes_per_copy": 2 * src.numel() * 4, "ms": round(ms_copy, 5),
                              "gb_s": round(2 * src.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
-    want = {"c1", "c3", "c4", "c5", "g1", "g4", "sweep", "u1", "p1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
+    want = {"c1", "c3", "c4", "c5", "g1", "g4", "sweep", "dims", "u1", "p1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
     rows = {}
-    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep), ("u1", row_u1), ("p1", row_p1)):
+    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep), ("dims", row_dims), ("u1", row_u1), ("p1", row_p1)):
         if name in want:
             rows[name] = fn(svd, torch, synth, args)
             print(f"row {name} done", file=sys.stderr, flush=True)

@@ -330,6 +330,24 @@ svdlut_status svdlut_paper_generator_bwd(const float* params, const uint8_t* kee
                                          int32_t Ds, void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * The other LUT dimensions the paper weighs the 2D decomposition against (Sec.
+ * "Preliminary" and the LUT-dimension analysis: a 3D LUT indexed by all three channels and
+ * per-channel 1D LUTs), as standalone float32 transforms of planar x [B][3][H][W] into y
+ * (same shape, must not alias x).  Inputs are clamped to [0, 1] and decoded like the 2D
+ * LUTs (q = x (D - 1) in float32, cell min(floor(q), D - 2)).
+ * svdlut_lut3d_apply: T3 [B][3][D][D][D], output channel c reads t^c[i_r][i_g][i_b] by
+ *   trilinear interpolation.  ws: svdlut_lut3d_workspace_size(B, D) bytes (the LUTs
+ *   repacked as one float4 per vertex).
+ * svdlut_lut1d_apply: T1 [B][3][D], y_c = linear interpolation of t_c at x_c.
+ * D in [2, 40].
+ */
+size_t svdlut_lut3d_workspace_size(int32_t B, int32_t D);
+svdlut_status svdlut_lut3d_apply(const float* x, float* y, const float* T3, int32_t B, int32_t H,
+                                 int32_t W, int32_t D, void* ws, size_t ws_bytes, hipStream_t stream);
+svdlut_status svdlut_lut1d_apply(const float* x, float* y, const float* T1, int32_t B, int32_t H,
+                                 int32_t W, int32_t D, hipStream_t stream);
+
+/*
  * svdlut_adam_step — one step of standard Adam (the paper trains with Adam, Sec.
  * "Application Settings"), in place on n float32 values:
  *   m = b1 m + (1-b1) g;  v = b2 v + (1-b2) g^2;

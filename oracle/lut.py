@@ -214,6 +214,21 @@ def trilinear(x, T3):
     return out
 
 
+def lut1d(x, T1):
+    """Per-channel 1D LUT (the lowest LUT dimension of the paper's LUT-dimension analysis):
+    Y_c = linear interpolation of the curve T1[c] (D vertices) at the decoded X_c.
+
+    x [3][H][W], T1 [3][D].  Returns float64 [3][H][W].
+    """
+    T1 = np.asarray(T1, dtype=np.float64)
+    D = T1.shape[1]
+    out = np.zeros(np.shape(x), dtype=np.float64)
+    for c in range(3):
+        i, d = decode(x[c], D)
+        out[c] = (1 - d) * T1[c][i] + d * T1[c][i + 1]
+    return out
+
+
 # ---------------------------------------------------------------- O7 backward
 def transform_bwd(x, T, smap, G):
     """Gradients of sum(G * Y) for one image by the chain rule of the forward above.

@@ -51,6 +51,9 @@ SIGS = {
     "svdlut_generator_workspace_size": (SZ, [I32, I32, I32]),
     "svdlut_generator_fwd": (I32, [P, P, I32, I32, I32, I32, I32, I32, P, P, P, P, P, SZ, P]),
     "svdlut_generator_bwd": (I32, [P, P, P, P, P, P, I32, I32, I32, P, SZ, P]),
+    "svdlut_lut3d_workspace_size": (SZ, [I32, I32]),
+    "svdlut_lut3d_apply": (I32, [P, P, P, I32, I32, I32, I32, P, SZ, P]),
+    "svdlut_lut1d_apply": (I32, [P, P, P, I32, I32, I32, I32, P]),
     "svdlut_paper_generator_param_count": (SZ, [I32, I32, I32, I32]),
     "svdlut_paper_generator_workspace_size": (SZ, [I32, I32, I32, I32, I32]),
     "svdlut_paper_generator_fwd": (I32, [P, P, I32, I32, I32, I32, I32, I32, I32, I32, P, P, P, P, P, P, P, P, P,

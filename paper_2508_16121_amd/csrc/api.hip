@@ -189,6 +189,29 @@ svdlut_status svdlut_unfused_apply(const float* x, float* y, const float* grids,
     return launch_unfused(a, stream);
 }
 
+size_t svdlut_lut3d_workspace_size(int32_t B, int32_t D) {
+    if (B < 1 || D < 2 || D > kMaxD) return 0;
+    return lut3d_workspace_bytes(B, D);
+}
+
+svdlut_status svdlut_lut3d_apply(const float* x, float* y, const float* T3, int32_t B, int32_t H, int32_t W,
+                                 int32_t D, void* ws, size_t ws_bytes, hipStream_t stream) {
+    if (!x || !y || !T3 || !ws) return fail(SVDLUT_EINVAL, "lut3d_apply: null pointer");
+    if (B < 1 || !dims_ok(H) || !dims_ok(W)) return fail(SVDLUT_EINVAL, "lut3d_apply: bad B, H or W");
+    if (D < 2 || D > kMaxD) return fail(SVDLUT_EINVAL, "lut3d_apply: D must be in [2, 40]");
+    if (ws_bytes < lut3d_workspace_bytes(B, D))
+        return fail(SVDLUT_EINVAL, "lut3d_apply: workspace smaller than svdlut_lut3d_workspace_size()");
+    return launch_lut3d(x, y, T3, B, H, W, D, ws, stream);
+}
+
+svdlut_status svdlut_lut1d_apply(const float* x, float* y, const float* T1, int32_t B, int32_t H, int32_t W,
+                                 int32_t D, hipStream_t stream) {
+    if (!x || !y || !T1) return fail(SVDLUT_EINVAL, "lut1d_apply: null pointer");
+    if (B < 1 || !dims_ok(H) || !dims_ok(W)) return fail(SVDLUT_EINVAL, "lut1d_apply: bad B, H or W");
+    if (D < 2 || D > kMaxD) return fail(SVDLUT_EINVAL, "lut1d_apply: D must be in [2, 40]");
+    return launch_lut1d(x, y, T1, B, H, W, D, stream);
+}
+
 size_t svdlut_apply_grid_bwd_workspace_size(int32_t B, int32_t D, int32_t Ds) {
     if (B < 1 || D < 2 || D > kMaxD || Ds < 2 || Ds > kMaxDs) return 0;
     return ((bwd_workspace_bytes(B, D) + 255) & ~static_cast<size_t>(255)) + grid_bwd_workspace_bytes(B, Ds);

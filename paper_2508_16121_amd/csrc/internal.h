@@ -133,6 +133,12 @@ struct UnfusedLaunch {
 size_t unfused_workspace_bytes(int B, int H, int W, int K, int D);
 svdlut_status launch_unfused(const UnfusedLaunch& a, hipStream_t st);
 
+// Standalone 3D-LUT (trilinear) and 1D-LUT (per-channel linear) transforms, fp32 planar.
+size_t lut3d_workspace_bytes(int B, int D);
+svdlut_status launch_lut3d(const float* x, float* y, const float* T3, int B, int H, int W, int D, void* ws,
+                           hipStream_t st);
+svdlut_status launch_lut1d(const float* x, float* y, const float* T1, int B, int H, int W, int D, hipStream_t st);
+
 // ---------------------------------------------------------------- generator
 svdlut_status launch_loss(const void* y, const void* t, svdlut_dtype io, int64_t n, int kind,
                           float* loss, void* dy, float* partial, int nblocks, hipStream_t st);

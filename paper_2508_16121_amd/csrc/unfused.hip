@@ -10,6 +10,11 @@
 //   fuse_kernel      reads X and f_s, writes X_bar (12 B/px)
 //   lut3d_kernel     reads X_bar, writes Y; the 3D LUTs packed as one float4 per vertex
 //                    (the three output channels and a pad) in the workspace, read through L2.
+//
+// The same file holds the other LUT dimensions the paper weighs the 2D decomposition against
+// (Sec. "Preliminary", the LUT-dimension analysis): a standalone 3D-LUT transform of X
+// (lut3d_kernel on the input) and a per-channel 1D-LUT transform (lut1d_kernel, the three
+// curves in LDS).
 #include "internal.h"
 #include "lut_common.h"
 
@@ -196,7 +201,61 @@ __global__ void __launch_bounds__(kUfBlock) lut3d_kernel(const float* __restrict
     }
 }
 
+// Y_c = linear interpolation of the 1D LUT t_c (D vertices) at X_c, per pixel.
+__global__ void __launch_bounds__(kUfBlock) lut1d_kernel(const float* __restrict__ x, float* __restrict__ y,
+                                                         const float* __restrict__ T1, int64_t n, int D) {
+    __shared__ float t[3 * (kMaxD + 1)];
+    const int b = blockIdx.y;
+    for (int i = threadIdx.x; i < 3 * D; i += blockDim.x) t[(i / D) * (kMaxD + 1) + i % D] = T1[b * 3 * D + i];
+    __syncthreads();
+    const float* xb = x + static_cast<int64_t>(b) * 3 * n;
+    float* yb = y + static_cast<int64_t>(b) * 3 * n;
+    const bool vec = (n & 3) == 0 && ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y)) & 15) == 0;
+    const float Dm1 = static_cast<float>(D - 1), Dm2 = static_cast<float>(D - 2);
+    for (int64_t p0 = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) * 4; p0 < n;
+         p0 += static_cast<int64_t>(gridDim.x) * blockDim.x * 4) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float px[4], out[4];
+            uf_load4(xb + c * n, p0, n, vec, px);
+            const float* tc = t + c * (kMaxD + 1);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                float f, d;
+                uf_decode(px[k], Dm1, Dm2, f, d);
+                const int i = static_cast<int>(f);
+                out[k] = fmaf(d, tc[i + 1] - tc[i], tc[i]);
+            }
+            uf_store4(yb + c * n, p0, n, vec, out);
+        }
+    }
+}
+
+int stream_blocks(int64_t n, int B) {
+    const DeviceInfo& di = device_info();
+    const int64_t quads = (n + 3) / 4;
+    return static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(
+        (quads + kUfBlock - 1) / kUfBlock, static_cast<int64_t>(di.cus) * 8 / std::max(B, 1) + 1)));
+}
+
 }  // namespace
+
+size_t lut3d_workspace_bytes(int B, int D) { return sizeof(float4) * static_cast<size_t>(B) * D * D * D; }
+
+svdlut_status launch_lut3d(const float* x, float* y, const float* T3, int B, int H, int W, int D, void* ws,
+                           hipStream_t st) {
+    const int64_t n = static_cast<int64_t>(H) * W;
+    float4* packed = static_cast<float4*>(ws);
+    hipLaunchKernelGGL(pack_lut3d_kernel, dim3(64), dim3(256), 0, st, T3, packed, B, D);
+    hipLaunchKernelGGL(lut3d_kernel, dim3(stream_blocks(n, B), B), dim3(kUfBlock), 0, st, x, y, packed, n, D);
+    return check_launch("lut3d_apply");
+}
+
+svdlut_status launch_lut1d(const float* x, float* y, const float* T1, int B, int H, int W, int D, hipStream_t st) {
+    const int64_t n = static_cast<int64_t>(H) * W;
+    hipLaunchKernelGGL(lut1d_kernel, dim3(stream_blocks(n, B), B), dim3(kUfBlock), 0, st, x, y, T1, n, D);
+    return check_launch("lut1d_apply");
+}
 
 size_t unfused_workspace_bytes(int B, int H, int W, int K, int D) {
     const size_t n = static_cast<size_t>(H) * W;

@@ -205,6 +205,40 @@ def apply_grid_bwd(x, dy, U, s, V, smap, grids, gw, need_dx=True, need_factors=T
     return out
 
 
+def lut3d_apply(x, T3, out=None, ws=None):
+    """Standalone 3D-LUT transform (svdlut_lut3d_apply): x [B][3][H][W] float32, T3
+    [B][3][D][D][D] float32 (output channel, then the r, g, b vertex indices)."""
+    _need(x, "x", ndim=4)
+    _need(T3, "T3", ndim=5)
+    B, _, H, W = x.shape
+    D = T3.shape[2]
+    if T3.shape != (B, 3, D, D, D):
+        raise ValueError("T3 must be [B][3][D][D][D]")
+    if out is None:
+        out = torch.empty_like(x)
+    lib = _lib.load()
+    if ws is None:
+        ws = torch.empty(lib.svdlut_lut3d_workspace_size(B, D) // 4 + 64, device=x.device, dtype=torch.float32)
+    check(lib.svdlut_lut3d_apply(_ptr(x), _ptr(out), _ptr(T3), B, H, W, D, _ptr(ws), ws.numel() * 4, _stream()),
+          "svdlut_lut3d_apply")
+    return out
+
+
+def lut1d_apply(x, T1, out=None):
+    """Per-channel 1D-LUT transform (svdlut_lut1d_apply): x [B][3][H][W], T1 [B][3][D], float32."""
+    _need(x, "x", ndim=4)
+    _need(T1, "T1", ndim=3)
+    B, _, H, W = x.shape
+    D = T1.shape[2]
+    if T1.shape != (B, 3, D):
+        raise ValueError("T1 must be [B][3][D]")
+    if out is None:
+        out = torch.empty_like(x)
+    check(_lib.load().svdlut_lut1d_apply(_ptr(x), _ptr(out), _ptr(T1), B, H, W, D, _stream()),
+          "svdlut_lut1d_apply")
+    return out
+
+
 def unfused_apply(x, grids, gw, gb, Wf, bf, T3, out=None, ws=None):
     """The unfused original structure (svdlut_unfused_apply): slicing -> f_s -> 1x1 fusion
     -> 3D LUT, float32.  grids [B][K][3][Ds][Ds], gw [B][K][3], gb [B][K], Wf [B][3][K+3],

@@ -116,6 +116,20 @@ def test_validation_happens_before_any_hip_call(lib):
     assert lib.svdlut_generator_bwd(fake, null, fake, fake, fake, fake, 1, 33, 8, fake, 1 << 30, null) == 1
 
 
+def test_lut_dims_validation(lib):
+    null = None
+    fake = C.c_void_p(0x1000)
+    assert lib.svdlut_lut3d_apply(null, fake, fake, 1, 8, 8, 33, fake, 1 << 30, null) == 1
+    assert lib.svdlut_lut3d_apply(fake, fake, fake, 1, 8, 8, 41, fake, 1 << 30, null) == 1
+    assert lib.svdlut_lut3d_apply(fake, fake, fake, 1, 8, 8, 33, fake, 16, null) == 1 and "workspace" in _err(lib)
+    assert lib.svdlut_lut3d_apply(fake, fake, fake, 0, 8, 8, 33, fake, 1 << 30, null) == 1
+    assert lib.svdlut_lut1d_apply(fake, fake, null, 1, 8, 8, 33, null) == 1
+    assert lib.svdlut_lut1d_apply(fake, fake, fake, 1, 0, 8, 33, null) == 1
+    assert lib.svdlut_lut1d_apply(fake, fake, fake, 1, 8, 8, 1, null) == 1
+    assert lib.svdlut_lut3d_workspace_size(2, 33) == 2 * 33 ** 3 * 16
+    assert lib.svdlut_lut3d_workspace_size(0, 33) == 0
+
+
 def test_paper_generator_validation(lib):
     null = None
     fake = C.c_void_p(0x1000)

@@ -478,3 +478,20 @@ def test_transform_at_matches_full_transform():
     ys = g.integers(0, 37, 200); xs = g.integers(0, 53, 200)
     ys[:2] = [0, 36]; xs[:2] = [0, 52]
     assert np.array_equal(ol.transform_at(x, T, m, ys, xs, [0.1, 0.2, 0.3]), full[:, ys, xs])
+
+
+def test_lut1d_matches_numpy_interp():
+    """The 1D-LUT oracle is numpy's piecewise-linear interpolation of the curve at the clamped
+    input (away from the float32 rounding of the cell index)."""
+    g = np.random.default_rng(61)
+    D = 33
+    T1 = g.normal(0, 1, (3, D))
+    x = g.uniform(-0.1, 1.1, (3, 20, 30))
+    got = ol.lut1d(x, T1)
+    knots = np.linspace(0, 1, D)
+    for c in range(3):
+        ref = np.interp(np.clip(x[c], 0, 1), knots, T1[c])
+        assert np.abs(got[c] - ref).max() <= 1e-6 * np.abs(T1).max()
+    # identity curve returns the clamped input
+    ident = np.tile(knots, (3, 1))
+    assert np.abs(ol.lut1d(x, ident) - np.clip(x, 0, 1)).max() <= 1e-7
