@@ -82,13 +82,22 @@ def measured_traffic():
 
 
 def launch_times(fn, steps, warmup, torch):
-    """(ms per step, ms per launch) over `steps` calls of a one-kernel fn(i).  Events on the
-    current stream (the stream the library launches on) bracket the whole timed region and,
-    in addition, every single launch, so the second figure is the kernel's own duration
-    without the host-side gaps between launches."""
+    """(ms per step, ms per launch) over `steps` calls of a one-kernel fn(i), both with HIP
+    events on the current stream (the stream the library launches on).  The first figure
+    brackets the whole run of `steps` back-to-back calls; the second comes from a separate run
+    in which every launch has its own event pair, i.e. the kernel's own duration without the
+    gaps between launches (the event packets themselves stay out of the first figure)."""
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for i in range(steps):
+        fn(i)
+    e1.record()
+    torch.cuda.synchronize()
+    per_step = e0.elapsed_time(e1) / steps
     ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * steps)]
     for i in range(steps):
         ev[2 * i].record()
@@ -96,7 +105,7 @@ def launch_times(fn, steps, warmup, torch):
         ev[2 * i + 1].record()
     torch.cuda.synchronize()
     per = sum(ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(steps)) / steps
-    return ev[0].elapsed_time(ev[-1]) / steps, per
+    return per_step, per
 
 
 def roof(bytes_alg, ms):

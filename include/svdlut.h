@@ -313,6 +313,9 @@ svdlut_status svdlut_generator_bwd(const float* params, const float* dU, const f
  *   K = 0).  Backward inputs have the same shapes; a NULL gradient counts as zero.  grads
  *   (out) has the layout of params and is overwritten.
  * K in [0, 12]; Ds in [2, 33] when K > 0; D in [2, 40]; R in [1, 64].
+ * The forward is deterministic (fixed-order reductions).  In the backward, convolution and FC
+ * weight gradients are reproducible; convolution biases and norm scale/shift gradients are
+ * summed with float atomics and may differ in the last bits between runs.
  */
 size_t svdlut_paper_generator_param_count(int32_t D, int32_t R, int32_t K, int32_t Ds);
 size_t svdlut_paper_generator_workspace_size(int32_t B, int32_t D, int32_t R, int32_t K, int32_t Ds);

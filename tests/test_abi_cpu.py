@@ -170,3 +170,18 @@ def test_size_queries(lib):
     assert lib.svdlut_paper_generator_param_count(33, 8, 13, 17) == 0
     assert lib.svdlut_paper_generator_workspace_size(8, 33, 8, 6, 17) > 0
     assert lib.svdlut_paper_generator_workspace_size(0, 33, 8, 6, 17) == 0
+
+
+def test_paper_generator_layout_matches_oracle(lib):
+    """The package's parameter layout of the paper's generator has the oracle's order and
+    shapes, and its size is the library's count."""
+    import numpy as np
+
+    from oracle import paper_generator as pg
+    from paper_2508_16121_amd import paper_model as pm
+    for K in (0, 6):
+        a = [s for _, s in pm.param_shapes(33, 8, K, 17)]
+        b = [s for _, s in pg.param_shapes(33, 8, K, 17)]
+        assert a == b
+        assert sum(int(np.prod(s)) for s in a) == lib.svdlut_paper_generator_param_count(33, 8, K, 17)
+        assert pm.init_params(33, 8, K, 17).size == lib.svdlut_paper_generator_param_count(33, 8, K, 17)
