@@ -227,3 +227,21 @@ class PaperTrainer:
         g.backward(up, m)
         self.opt.step(g.grads)
         return lval
+
+    def state_dict(self):
+        return {"params": self.gen.params.detach().cpu().numpy(), "m": self.opt.m.cpu().numpy(),
+                "v": self.opt.v.cpu().numpy(), "t": self.opt.t, "rng": self._rng.get_state().cpu().numpy()}
+
+    def load_state_dict(self, st):
+        self.gen.params.copy_(torch.as_tensor(st["params"]))
+        self.opt.m.copy_(torch.as_tensor(st["m"]))
+        self.opt.v.copy_(torch.as_tensor(st["v"]))
+        self.opt.t = int(st["t"])
+        self._rng.set_state(torch.as_tensor(st["rng"], dtype=torch.uint8))
+
+    def save(self, path):
+        np.savez(path, **{k: np.asarray(v) for k, v in self.state_dict().items()})
+
+    def load(self, path):
+        with np.load(path, allow_pickle=False) as z:
+            self.load_state_dict({k: z[k] for k in z.files})

@@ -224,3 +224,35 @@ def test_paper_model_training_gain(PM, pair_data):
         f"({steps} steps x {batch}, {t1 - t0:.1f}s)")
     assert np.isfinite(p_model)
     assert p_model >= p_id + 0.5
+
+
+def test_paper_trainer_checkpoint_resume(PM, pair_data, tmp_path):
+    """N steps, save (parameters, Adam state, dropout generator state), reload into fresh
+    objects, N more steps vs 2N uninterrupted: as close as two uninterrupted runs are to each
+    other (float atomics in a few bias/norm gradients), far from a run without the checkpoint."""
+    import os
+    xtr, ttr, _, _ = pair_data
+    n, batch = 15, 16
+
+    def run(steps, tr, skip=0):
+        g = np.random.default_rng(9)
+        for it in range(steps):
+            idx = torch.from_numpy(g.integers(0, xtr.shape[0], batch)).cuda()
+            if it >= skip:
+                tr.step(xtr.index_select(0, idx).contiguous(), ttr.index_select(0, idx).contiguous())
+        torch.cuda.synchronize()
+
+    ga = PM.PaperGenerator(seed=5); run(2 * n, PM.PaperTrainer(ga, seed=3))
+    ga2 = PM.PaperGenerator(seed=5); run(2 * n, PM.PaperTrainer(ga2, seed=3))
+    gb = PM.PaperGenerator(seed=5); trb = PM.PaperTrainer(gb, seed=3); run(n, trb)
+    path = os.path.join(tmp_path, "paper_ckpt.npz")
+    trb.save(path)
+    gc = PM.PaperGenerator(seed=123)
+    trc = PM.PaperTrainer(gc, seed=77)
+    trc.load(path)
+    run(2 * n, trc, skip=n)
+    a, a2, b, c = (host(x.params) for x in (ga, ga2, gb, gc))
+    assert trc.opt.t == 2 * n
+    noise = np.abs(a - a2).mean()
+    assert np.abs(a - c).mean() <= 3 * noise + 1e-7
+    assert np.abs(a - b).mean() > 10 * (np.abs(a - c).mean() + 1e-9)
