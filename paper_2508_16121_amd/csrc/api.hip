@@ -137,6 +137,9 @@ static svdlut_status apply_impl(const void* x, void* y, svdlut_dtype io, const f
     const int lds_ds = K > 0 ? Ds : 0;
     a.block = default_block(D, R, a.ncol_max, di, lds_ds);
     if (a.block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply: map too wide for LDS staging");
+    // small frames: narrower workgroups, so that the tiles (one per wave at least) spread over
+    // every CU instead of filling a few 16-wave workgroups
+    while (a.block > kWave && a.total_tiles < static_cast<int64_t>(di.cus) * (a.block / kWave)) a.block /= 2;
     const int64_t max_grid = static_cast<int64_t>(di.cus) * blocks_per_cu(D, R, a.block, a.ncol_max, di, lds_ds);
     const int64_t tiles_per_block_min = a.block / kWave;   // at least one tile per wave
     a.grid = static_cast<int>(std::max<int64_t>(1, std::min(max_grid, (a.total_tiles + tiles_per_block_min - 1) / tiles_per_block_min)));
