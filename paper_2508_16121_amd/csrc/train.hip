@@ -17,7 +17,38 @@ template <typename T> __device__ __forceinline__ T fromf(float v);
 template <> __device__ __forceinline__ float fromf<float>(float v) { return v; }
 template <> __device__ __forceinline__ __half fromf<__half>(float v) { return __float2half_rn(v); }
 
-// Stage 1: per-block partial sums (fixed grid-stride order) and the gradient.
+// Four consecutive elements as floats (vector access: float4 for fp32, 8 bytes for fp16).
+__device__ __forceinline__ void ld4(const float* p, float (&o)[4]) {
+    const float4 v = *reinterpret_cast<const float4*>(p);
+    o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
+}
+__device__ __forceinline__ void ld4(const __half* p, float (&o)[4]) {
+    const uint2 v = *reinterpret_cast<const uint2*>(p);
+    const __half2 a = *reinterpret_cast<const __half2*>(&v.x), b = *reinterpret_cast<const __half2*>(&v.y);
+    o[0] = __low2float(a); o[1] = __high2float(a); o[2] = __low2float(b); o[3] = __high2float(b);
+}
+__device__ __forceinline__ void st4(float* p, const float (&o)[4]) {
+    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+}
+__device__ __forceinline__ void st4(__half* p, const float (&o)[4]) {
+    const __half2 a = __floats2half2_rn(o[0], o[1]), b = __floats2half2_rn(o[2], o[3]);
+    uint2 v;
+    v.x = *reinterpret_cast<const uint32_t*>(&a);
+    v.y = *reinterpret_cast<const uint32_t*>(&b);
+    *reinterpret_cast<uint2*>(p) = v;
+}
+
+__device__ __forceinline__ float loss_term(float d, int kind, float invn, float& g) {
+    if (kind == SVDLUT_LOSS_L1) {
+        g = d > 0.f ? invn : (d < 0.f ? -invn : 0.f);
+        return fabsf(d);
+    }
+    g = 2.f * d * invn;
+    return d * d;
+}
+
+// Stage 1: per-block partial sums (fixed grid-stride order over groups of four elements,
+// vector loads when the buffers allow) and the gradient.
 template <typename T>
 __global__ void __launch_bounds__(kLossThreads) loss_partial_kernel(const T* __restrict__ y,
                                                                      const T* __restrict__ t, int64_t n,
@@ -25,17 +56,37 @@ __global__ void __launch_bounds__(kLossThreads) loss_partial_kernel(const T* __r
                                                                      float* __restrict__ partial) {
     __shared__ float red[kLossThreads / 64];
     const float invn = 1.f / static_cast<float>(n);
+    constexpr uintptr_t kAlign = 4 * sizeof(T) - 1;
+    const bool vec = ((reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(t) |
+                       reinterpret_cast<uintptr_t>(dy)) & kAlign) == 0;
+    const int64_t n4 = n / 4;
+    const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
     float acc = 0.f;
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const float d = tof<T>(y[i]) - tof<T>(t[i]);
-        if (kind == SVDLUT_LOSS_L1) {
-            acc += fabsf(d);
-            if (dy) dy[i] = fromf<T>(d > 0.f ? invn : (d < 0.f ? -invn : 0.f));
+    for (int64_t q = tid; q < n4; q += stride) {
+        const int64_t i = 4 * q;
+        float a[4], b[4], g[4];
+        if (vec) {
+            ld4(y + i, a);
+            ld4(t + i, b);
         } else {
-            acc = fmaf(d, d, acc);
-            if (dy) dy[i] = fromf<T>(2.f * d * invn);
+#pragma unroll
+            for (int k = 0; k < 4; ++k) { a[k] = tof<T>(y[i + k]); b[k] = tof<T>(t[i + k]); }
         }
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc += loss_term(a[k] - b[k], kind, invn, g[k]);
+        if (dy) {
+            if (vec) st4(dy + i, g);
+            else
+#pragma unroll
+                for (int k = 0; k < 4; ++k) dy[i + k] = fromf<T>(g[k]);
+        }
+    }
+    if (tid < n - 4 * n4) {               // the last n mod 4 elements
+        const int64_t i = 4 * n4 + tid;
+        float g;
+        acc += loss_term(tof<T>(y[i]) - tof<T>(t[i]), kind, invn, g);
+        if (dy) dy[i] = fromf<T>(g);
     }
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = acc;

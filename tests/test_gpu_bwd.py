@@ -91,6 +91,26 @@ def test_loss_kernels(svd):
         assert np.abs(host(dy) - rdy).max() <= 1e-6 * np.abs(rdy).max()
 
 
+def test_loss_kernels_fp16_and_unaligned(svd):
+    """fp16 storage (8-byte vector path) and buffers that start off a 16-byte boundary (the
+    element path), each with a ragged tail of n mod 4 elements."""
+    g = np.random.default_rng(3)
+    n = 4 * 1234 + 3
+    y = g.uniform(0, 1, n + 1).astype(np.float32)
+    t = g.uniform(0, 1, n + 1).astype(np.float32)
+    for kind, fn in (("l1", ol.l1_loss), ("mse", ol.mse_loss)):
+        yd, td = dev(y)[1:], dev(t)[1:]                      # 4-byte offset: not 16-byte aligned
+        v, dy = svd.loss(yd, td, kind)
+        rv, rdy = fn(y[1:], t[1:])
+        assert abs(host(v)[0] - rv) <= 1e-5 * max(1.0, abs(rv))
+        assert np.abs(host(dy) - rdy).max() <= 1e-6 * np.abs(rdy).max()
+        yh, th = y[:n].astype(np.float16), t[:n].astype(np.float16)
+        v, dy = svd.loss(dev(yh), dev(th), kind)
+        rv, rdy = fn(yh.astype(np.float64), th.astype(np.float64))
+        assert abs(host(v)[0] - rv) <= 1e-4 * max(1.0, abs(rv))
+        assert np.abs(host(dy) - rdy).max() <= 2e-3 * np.abs(rdy).max()
+
+
 def test_autograd_matches_apply_bwd(svd):
     c = synth.single(41, 40, 72, 17, 4, 5, 9)
     x, U, s, V, m = (dev(a).requires_grad_() for a in (c.x, c.U, c.s, c.V, c.smap))
