@@ -16,12 +16,22 @@ __device__ __forceinline__ void gbl_add(float* p, float v) {
 }
 __device__ __forceinline__ int fix(float v) { return __float2int_rn(v); }
 
+// round(a * b) to the nearest integer (ties to even) for |a * b| < 2^22, in two instructions:
+// one fma adds 1.5 * 2^23, whose ulp is 1, so the exact product is rounded once and lands in
+// the low mantissa bits, which an integer subtraction takes out.  The scales from fix_scale
+// keep every accumulated term below 2^22.
+__device__ __forceinline__ int fix_mul(float a, float b) {
+    return __float_as_int(fmaf(a, b, 12582912.0f)) - 0x4B400000;
+}
+
 // Largest power of two 2^e with n * m1 * m2 * 2^e < 2^30 (1 when a factor is 0); sets
-// `bad` when the bound does not fit the float exponent range.
+// `bad` when the bound does not fit the float exponent range.  n counts as at least 1024, so
+// a single term (or a sum of up to four terms merged in registers) stays below 2^22, the
+// range of fix_mul.
 __device__ inline float fix_scale(float n, float m1, float m2, bool& bad) {
     if (!(n > 0.f) || !(m1 > 0.f) || !(m2 > 0.f)) return 1.f;
     int en, e1, e2;
-    frexpf(n, &en);
+    frexpf(fmaxf(n, 1024.f), &en);
     frexpf(m1, &e1);
     frexpf(m2, &e2);
     const int e = 30 - (en + e1 + e2);   // each factor f < 2^ef

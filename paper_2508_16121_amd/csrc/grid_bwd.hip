@@ -84,10 +84,10 @@ __device__ __forceinline__ void grid_bwd_tile(const GridBwdDev& P, int b, int y,
             } else if (P.want_g) {            // tiny images: more than one vertex per pixel step
                 int* A = Al + (3 * c) * PL;
                 const float g0 = G * (1.f - wx) * sc, g1 = G * wx * sc;
-                lds_addi(A + ixk * Dsp + iy, fix(g0 * (1.f - wy)));
-                lds_addi(A + ixk * Dsp + iy + 1, fix(g0 * wy));
-                lds_addi(A + (ixk + 1) * Dsp + iy, fix(g1 * (1.f - wy)));
-                lds_addi(A + (ixk + 1) * Dsp + iy + 1, fix(g1 * wy));
+                lds_addi(A + ixk * Dsp + iy, fix_mul(g0, 1.f - wy));
+                lds_addi(A + ixk * Dsp + iy + 1, fix_mul(g0, wy));
+                lds_addi(A + (ixk + 1) * Dsp + iy, fix_mul(g1, 1.f - wy));
+                lds_addi(A + (ixk + 1) * Dsp + iy + 1, fix_mul(g1, wy));
             }
             // xc and yc planes
             if (P.want_g) {
@@ -95,14 +95,14 @@ __device__ __forceinline__ void grid_bwd_tile(const GridBwdDev& P, int b, int y,
                 int* Axc = Al + (3 * c + 1) * PL + ixk * Dsp + ic;
                 int* Ayc = Al + (3 * c + 2) * PL + iy * Dsp + ic;
                 const float wc0 = gs * (1.f - wc), wc1 = gs * wc;
-                lds_addi(Axc, fix(wc0 * (1.f - wx)));
-                lds_addi(Axc + 1, fix(wc1 * (1.f - wx)));
-                lds_addi(Axc + Dsp, fix(wc0 * wx));
-                lds_addi(Axc + Dsp + 1, fix(wc1 * wx));
-                lds_addi(Ayc, fix(wc0 * (1.f - wy)));
-                lds_addi(Ayc + 1, fix(wc1 * (1.f - wy)));
-                lds_addi(Ayc + Dsp, fix(wc0 * wy));
-                lds_addi(Ayc + Dsp + 1, fix(wc1 * wy));
+                lds_addi(Axc, fix_mul(wc0, 1.f - wx));
+                lds_addi(Axc + 1, fix_mul(wc1, 1.f - wx));
+                lds_addi(Axc + Dsp, fix_mul(wc0, wx));
+                lds_addi(Axc + Dsp + 1, fix_mul(wc1, wx));
+                lds_addi(Ayc, fix_mul(wc0, 1.f - wy));
+                lds_addi(Ayc + 1, fix_mul(wc1, 1.f - wy));
+                lds_addi(Ayc + Dsp, fix_mul(wc0, wy));
+                lds_addi(Ayc + Dsp + 1, fix_mul(wc1, wy));
             }
             // dx through the colour axis of the combined xc and yc planes
             const float* Cxc = Cl + (3 * c + 1) * PL + ixk * Dsp + ic;
@@ -121,8 +121,8 @@ __device__ __forceinline__ void grid_bwd_tile(const GridBwdDev& P, int b, int y,
             for (int n = 0; n < 3; ++n) {
                 if (ix0 + n > Ds - 1 || ax[c][n] == 0.f) continue;
                 const float v = ax[c][n] * sc;
-                lds_addi(A + (ix0 + n) * Dsp + iy, fix(v * (1.f - wy)));
-                lds_addi(A + (ix0 + n) * Dsp + iy + 1, fix(v * wy));
+                lds_addi(A + (ix0 + n) * Dsp + iy, fix_mul(v, 1.f - wy));
+                lds_addi(A + (ix0 + n) * Dsp + iy + 1, fix_mul(v, wy));
             }
         }
     }

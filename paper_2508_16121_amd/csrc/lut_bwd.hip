@@ -197,10 +197,10 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
                         int* q0 = dTl + slot;
                         int* q1 = q0 + rowstep;
                         const float gs = g * sT;
-                        lds_addi(q0 + c, fix(gs * w00));
-                        lds_addi(q1 + c, fix(gs * w10));
-                        lds_addi(q0 + kNode + c, fix(gs * w01));
-                        lds_addi(q1 + kNode + c, fix(gs * w11));
+                        lds_addi(q0 + c, fix_mul(gs, w00));
+                        lds_addi(q1 + c, fix_mul(gs, w10));
+                        lds_addi(q0 + kNode + c, fix_mul(gs, w01));
+                        lds_addi(q1 + kNode + c, fix_mul(gs, w11));
                     }
                     gx[al] = fmaf(g, (1.f - db) * (T10 - T00) + db * (T11 - T01), gx[al]);
                     gx[be] = fmaf(g, (1.f - da) * (T01 - T00) + da * (T11 - T10), gx[be]);
@@ -217,8 +217,8 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
                             A2[l] = fmaf(gp, tb, A2[l]);
                         } else {
                             const float gps = gp * sM;
-                            lds_addi(dstage + jk * kBwdStride + l, fix(gps * (1.f - du)));
-                            lds_addi(dstage + jk1 * kBwdStride + l, fix(gps * du));
+                            lds_addi(dstage + jk * kBwdStride + l, fix_mul(gps, 1.f - du));
+                            lds_addi(dstage + jk1 * kBwdStride + l, fix_mul(gps, du));
                         }
                     }
                 }
@@ -232,9 +232,9 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
         if (FASTMAP && P.want_dmap) {
 #pragma unroll
             for (int l = 0; l < 9; ++l) {
-                lds_addi(dstage + j0 * kBwdStride + l, fix(A0[l] * sM));
-                lds_addi(dstage + j1 * kBwdStride + l, fix(A1[l] * sM));
-                lds_addi(dstage + j2 * kBwdStride + l, fix(A2[l] * sM));
+                lds_addi(dstage + j0 * kBwdStride + l, fix_mul(A0[l], sM));
+                lds_addi(dstage + j1 * kBwdStride + l, fix_mul(A1[l], sM));
+                lds_addi(dstage + j2 * kBwdStride + l, fix_mul(A2[l], sM));
             }
         }
         if (P.want_dx) {
