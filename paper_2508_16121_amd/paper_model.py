@@ -138,7 +138,10 @@ class PaperGenerator:
     def backward(self, g, keep_mask=None):
         """Parameter gradients (into self.grads) from upstream gradients g (keys of forward's
         output; a missing key counts as zero) and the forward's keep mask."""
-        B = next(v for v in g.values() if v is not None).shape[0]
+        present = [v for v in g.values() if v is not None]
+        if not present:
+            raise ValueError("backward needs at least one upstream gradient")
+        B = present[0].shape[0]
         ws = self.workspace(B)
         for k, v in g.items():
             if v is not None:

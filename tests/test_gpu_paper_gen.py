@@ -72,7 +72,7 @@ def gpu_out_to_oracle_keys(o):
 
 
 @pytest.mark.parametrize("K,hw,use_mask", [(6, (256, 256), True), (6, (300, 280), False), (0, (200, 330), True),
-                                           (3, (64, 64), True)])
+                                           (3, (64, 64), True), (12, (1, 1), False), (1, (5, 700), True)])
 def test_paper_generator_forward_parity(PM, K, hw, use_mask):
     say(f"paper generator forward K={K} hw={hw} mask={use_mask}")
     P = rand_params(100 + K, K)
