@@ -288,9 +288,17 @@ def row_c4(svd, torch, synth, args):
         _, dy = svd.loss(d["y"], d["target"], "l1")
         svd.apply_bwd(d["x"], dy, d["U"], d["s"], d["V"], d["smap"], ws=d["ws"])
 
+    for d in sets:
+        d["lws"] = svd.loss_bwd_workspace(B, 33, "cuda")
+
+    def fused(i):
+        d = sets[i % N_ROT]
+        svd.apply_loss_bwd(d["x"], d["target"], d["U"], d["s"], d["V"], d["smap"], kind="l1", ws=d["lws"])
+
     steps = max(5, args.steps // 4)
     ms_f = event_time(fwd, steps, 3, torch)
     ms_fb = event_time(fwd_bwd, steps, 3, torch)
+    ms_fused = event_time(fused, steps, 3, torch)
     # algorithmic bytes: forward 24.56 B/px; loss 24 B/px (y, target read, dy written);
     # backward x 12 + dy 12 + dx 12 B/px plus the map and its gradient
     mapb = B * 9 * 64 * 64 * 4
@@ -299,7 +307,10 @@ def row_c4(svd, torch, synth, args):
     return {"workload": "16x3x512x512 fp32, D=33 R=8, map 9x64x64: apply + L1 loss + apply_bwd (dU ds dV dmap dx)",
             "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4),
             "fwd_mpix_s": round(npx / (ms_f * 1e-3) / 1e6, 1), "fwd_bwd_mpix_s": round(npx / (ms_fb * 1e-3) / 1e6, 1),
-            "fwd_roofline": roof(b_fwd, ms_f), "fwd_bwd_roofline": roof(b_fb, ms_fb)}
+            "fwd_roofline": roof(b_fwd, ms_f), "fwd_bwd_roofline": roof(b_fb, ms_fb),
+            # the same step as one fused pass (svdlut_apply_loss_bwd): x, target in; dx out
+            "fused_loss_bwd_ms": round(ms_fused, 4), "fused_mpix_s": round(npx / (ms_fused * 1e-3) / 1e6, 1),
+            "fused_roofline": roof(npx * 36 + 2 * mapb, ms_fused)}
 
 
 def row_g4(svd, torch, synth, args):

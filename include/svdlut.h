@@ -247,6 +247,27 @@ svdlut_status svdlut_loss(const void* y, const void* target, svdlut_dtype io, in
                           void* ws, size_t ws_bytes, hipStream_t stream);
 
 /*
+ * svdlut_apply_loss_bwd — one training pass of the transform fused in a single kernel: the
+ * forward output Y of svdlut_apply (bias nullable), the mean L1 or MSE loss of Y against
+ * target (loss, one float32, device), dL/dY formed per pixel (L1: sign(Y - t)/n with
+ * sign(0) = 0; MSE: 2 (Y - t)/n; n = B*3*H*W), and the gradients of svdlut_apply_bwd for that
+ * dL/dY.  The results equal svdlut_apply + svdlut_loss + svdlut_apply_bwd up to float
+ * rounding; Y and dL/dY are not written.  Layouts, nullability of dx / dU,ds,dV / dmap /
+ * dbias and the determinism notes are those of svdlut_apply_bwd; the loss is summed per
+ * workgroup and then in a fixed order, so it is reproducible.
+ * ws: svdlut_apply_loss_bwd_workspace_size(B, D) bytes (the dT partials and the loss partials).
+ */
+size_t svdlut_apply_loss_bwd_workspace_size(int32_t B, int32_t D);
+svdlut_status svdlut_apply_loss_bwd(const void* x, const void* target, svdlut_dtype io,
+                                    const float* U, const float* s, const float* V,
+                                    const void* map, svdlut_dtype map_dt, const float* bias,
+                                    svdlut_loss_kind kind, float* loss, void* dx,
+                                    float* dU, float* ds, float* dV, float* dmap, float* dbias,
+                                    int32_t B, int32_t H, int32_t W, int32_t h, int32_t w,
+                                    int32_t D, int32_t R, void* ws, size_t ws_bytes,
+                                    hipStream_t stream);
+
+/*
  * Learned generator of the factors and the spatial map from a downsampled image (the
  * paper's backbone + LUT generator, Sec. "Preliminary" Eq. backbone and supplementary
  * Tables backbone / gen_lut, sized as a small CNN):

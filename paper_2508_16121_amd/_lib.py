@@ -51,6 +51,9 @@ SIGS = {
     "svdlut_generator_workspace_size": (SZ, [I32, I32, I32]),
     "svdlut_generator_fwd": (I32, [P, P, I32, I32, I32, I32, I32, I32, P, P, P, P, P, SZ, P]),
     "svdlut_generator_bwd": (I32, [P, P, P, P, P, P, I32, I32, I32, P, SZ, P]),
+    "svdlut_apply_loss_bwd_workspace_size": (SZ, [I32, I32]),
+    "svdlut_apply_loss_bwd": (I32, [P, P, I32, P, P, P, P, I32, P, I32, P, P, P, P, P, P, P, I32, I32, I32, I32, I32,
+                                    I32, I32, P, SZ, P]),
     "svdlut_lut3d_workspace_size": (SZ, [I32, I32]),
     "svdlut_lut3d_apply": (I32, [P, P, P, I32, I32, I32, I32, P, SZ, P]),
     "svdlut_lut1d_apply": (I32, [P, P, P, I32, I32, I32, I32, P]),

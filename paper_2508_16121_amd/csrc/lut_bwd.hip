@@ -39,6 +39,11 @@ struct BwdDev {
     int mrows;          // map rows held per workgroup (0: flush dmap straight to global)
     int fast_map;
     int want_dT, want_dmap, want_dx, want_db;
+    // fused loss (svdlut_apply_loss_bwd): a.dy holds the target and dy = dL/dy is formed per
+    // pixel from the recomputed output
+    const float* bias;  // forward bias [B][3] (nullable)
+    float inv_n;        // 1 / (B * 3 * H * W)
+    float* lpart;       // per-workgroup loss partial sums [B * gpi]
 };
 
 // Geometry shared by all tiles of a workgroup.
@@ -51,11 +56,12 @@ struct BwdGeo {
 // One tile (row y, 256-pixel segment seg) of the backward.  The staged raw map rows (the
 // nine channels of rows iv and iv+1 for the segment's columns) are kept per wave and only
 // reloaded when the wave moves to another segment or another pair of map rows.
-template <typename IO, typename MT, bool FASTMAP, bool VEC>
+template <typename IO, typename MT, bool FASTMAP, bool VEC, int LOSS>
 __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b, int y, int seg,
                                          const float* Tl, int* dTl, int* macc, int row_lo,
                                          float* raw, float* stage, int* dstage, int& st_seg, int& st_iv,
-                                         float sT, float sM, float iM, float (&dbsum)[3]) {
+                                         float sT, float sM, float iM, float (&dbsum)[3],
+                                         const float (&bias3)[3], float& lacc) {
     const BwdLaunch& a = P.a;
     const int lane = threadIdx.x & (kWave - 1);
     const int H = a.H, W = a.W, h = a.h, w = a.w, D = a.D;
@@ -174,6 +180,42 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
             int ii[3]; float dd[3];
 #pragma unroll
             for (int c = 0; c < 3; ++c) decode(px[c][k], Dm1, Dm2, ii[c], dd[c]);
+            if (LOSS) {
+                // forward output of this pixel (Y_c = sum_p S_{3c+p} phi_{3c+p} + b_c), the loss
+                // term against the target held in gy, and dL/dy in its place
+                float yv[3] = {bias3[0], bias3[1], bias3[2]};
+#pragma unroll
+                for (int p = 0; p < 3; ++p) {
+                    const int al = (p == 2) ? 1 : 0;
+                    const int be = (p == 0) ? 1 : 2;
+                    const float da = dd[al], db = dd[be];
+                    const float w11 = da * db;
+                    const float w10 = da - w11;
+                    const float w01 = db - w11;
+                    const float w00 = 1.f - da - db + w11;
+                    const float* t0 = Tl + p * pairstep + ii[al] * rowstep + kNode * ii[be];
+                    const float* t1 = t0 + rowstep;
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        float phi = w00 * t0[c];
+                        phi = fmaf(w10, t1[c], phi);
+                        phi = fmaf(w01, t0[kNode + c], phi);
+                        phi = fmaf(w11, t1[kNode + c], phi);
+                        yv[c] = fmaf(S[3 * c + p], phi, yv[c]);
+                    }
+                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const float d = yv[c] - gy[c][k];
+                    if (LOSS == 1) {
+                        lacc += fabsf(d);
+                        gy[c][k] = d > 0.f ? P.inv_n : (d < 0.f ? -P.inv_n : 0.f);
+                    } else {
+                        lacc = fmaf(d, d, lacc);
+                        gy[c][k] = 2.f * d * P.inv_n;
+                    }
+                }
+            }
             float gx[3] = {0.f, 0.f, 0.f};
 #pragma unroll
             for (int c = 0; c < 3; ++c) dbsum[c] += gy[c][k];
@@ -269,7 +311,7 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
     }
 }
 
-template <typename IO, typename MT, bool FASTMAP>
+template <typename IO, typename MT, bool FASTMAP, int LOSS>
 __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     extern __shared__ float smem[];
     const BwdLaunch& a = P.a;
@@ -314,21 +356,29 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     const int64_t plane = static_cast<int64_t>(a.H) * a.W;
     float sT = 1.f, sM = 1.f;
     bool bad = false;
+    float bias3[3] = {0.f, 0.f, 0.f};
+    if (LOSS && P.bias) {
+#pragma unroll
+        for (int c = 0; c < 3; ++c) bias3[c] = P.bias[3 * b + c];
+    }
     if ((P.want_dT || P.want_dmap) && t0 < t1) {
         float mdy = 0.f, mmap = 0.f, mT = 0.f;
         bool nf = false;
         const int64_t e0 = (t0 / nseg) * a.W + (t0 % nseg) * kSeg;
         const int64_t e1 = ((t1 - 1) / nseg) * a.W + min(((t1 - 1) % nseg) * kSeg + kSeg, static_cast<int64_t>(a.W));
         const IO* dyb = reinterpret_cast<const IO*>(a.dy) + static_cast<int64_t>(b) * 3 * plane;
-        for (int c = 0; c < 3; ++c) absmax_range<IO>(dyb + c * plane + e0, e1 - e0, mdy, nf);
-        if (P.want_dT) {
+        // dy given: its band maximum.  L1: |dy| <= 1/n.  MSE: |dy| = 2 |y - t| / n with
+        // |y_c| <= 3 max|map| max|T| + |b_c| and the band maximum of the target.
+        if (LOSS != 1)
+            for (int c = 0; c < 3; ++c) absmax_range<IO>(dyb + c * plane + e0, e1 - e0, mdy, nf);
+        if (P.want_dT || LOSS == 2) {
             const int64_t mplane = static_cast<int64_t>(a.h) * a.w;
             const MT* mb = reinterpret_cast<const MT*>(a.map) + static_cast<int64_t>(b) * 9 * mplane +
                            static_cast<int64_t>(row_lo) * a.w;
             for (int l = 0; l < 9; ++l)
                 absmax_range<MT>(mb + l * mplane, static_cast<int64_t>(row_hi - row_lo + 1) * a.w, mmap, nf);
         }
-        if (P.want_dmap) {
+        if (P.want_dmap || LOSS == 2) {
             const int RS = lut_row_stride(D), PS = lut_pair_stride(D);
             for (int e = threadIdx.x; e < 9 * D * D; e += blockDim.x) {
                 const int l = e / (D * D), r = e - l * (D * D);
@@ -342,6 +392,12 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
         mmap = block_max(mmap, aux);
         mT = block_max(mT, aux);
         bad = block_max(nf ? 1.f : 0.f, aux) > 0.f;
+        if (LOSS == 1) mdy = P.inv_n;
+        if (LOSS == 2) {
+            const float mb = fmaxf(fabsf(bias3[0]), fmaxf(fabsf(bias3[1]), fabsf(bias3[2])));
+            mdy = 2.f * (3.f * mmap * mT + mb + mdy) * P.inv_n;
+            bad = bad || !(mdy <= FLT_MAX);
+        }
         const float n = static_cast<float>((t1 - t0) * kSeg);
         sT = fix_scale(n, mdy, mmap, bad);
         sM = fix_scale(n, mdy, mT, bad);
@@ -349,6 +405,7 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     const float iT = 1.f / sT, iM = 1.f / sM;
 
     float dbsum[3] = {0.f, 0.f, 0.f};
+    float lacc = 0.f;
     const bool base_ok = ((plane | a.W) & 3) == 0 &&
                          ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.dy) |
                            reinterpret_cast<uintptr_t>(a.dx)) & (4 * sizeof(IO) - 1)) == 0;
@@ -375,11 +432,11 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
             const int64_t lt = static_cast<int64_t>(y) * nseg + seg;
             if (lt < t0 || lt >= t1) continue;
             if (base_ok && seg * kSeg + kSeg <= a.W)
-                bwd_tile<IO, MT, FASTMAP, true>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage, dstage,
-                                                st_seg, st_iv, sT, sM, iMx, dbsum);
+                bwd_tile<IO, MT, FASTMAP, true, LOSS>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage, dstage,
+                                                      st_seg, st_iv, sT, sM, iMx, dbsum, bias3, lacc);
             else
-                bwd_tile<IO, MT, FASTMAP, false>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage, dstage,
-                                                 st_seg, st_iv, sT, sM, iMx, dbsum);
+                bwd_tile<IO, MT, FASTMAP, false, LOSS>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage, dstage,
+                                                       st_seg, st_iv, sT, sM, iMx, dbsum, bias3, lacc);
         }
     }
     __syncthreads();
@@ -411,6 +468,25 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
             if ((threadIdx.x & 63) == 0) gbl_add(a.dbias + 3 * b + c, v);
         }
     }
+    if (LOSS) {
+        // this workgroup's loss sum: lanes, then waves in order (aux is free after the barrier)
+        for (int off = 32; off > 0; off >>= 1) lacc += __shfl_xor(lacc, off, 64);
+        if ((threadIdx.x & 63) == 0) aux[wave] = lacc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float s = 0.f;
+            for (int i = 0; i < nw; ++i) s += aux[i];
+            P.lpart[lb] = s;
+        }
+    }
+}
+
+// loss = inv_n * sum of the per-workgroup partials, in order (fp64).
+__global__ void loss_sum_kernel(const float* __restrict__ part, int n, float inv_n, float* __restrict__ out) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) acc += part[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (threadIdx.x == 0) out[0] = static_cast<float>(acc * static_cast<double>(inv_n));
 }
 
 // Sum the per-workgroup dT partials (fixed order) and apply the chain rule of
@@ -499,10 +575,25 @@ static size_t bwd_lds(int D, int block, int ncol_max, int mrows, int w, int R) {
     return sizeof(float) * (2 * nlut + macc + std::max(stage, scratch));
 }
 
-svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
+// Fused loss of svdlut_apply_loss_bwd: kind (1 = L1, 2 = MSE), forward bias, partial sums
+// and the output value.
+struct LossArgs {
+    int kind;
+    const float* bias;
+    float* lpart;
+    float* loss;
+};
+
+static svdlut_status launch_bwd_impl(const BwdLaunch& a, const LossArgs* L, hipStream_t st) {
     const DeviceInfo& di = device_info();
-    BwdDev P;
+    BwdDev P{};
     P.a = a;
+    const int loss = L ? L->kind : 0;
+    if (L) {
+        P.bias = L->bias;
+        P.lpart = L->lpart;
+        P.inv_n = static_cast<float>(1.0 / (3.0 * static_cast<double>(a.B) * a.H * a.W));
+    }
     P.gpi = bwd_groups_per_image(a.B);
     const int nseg = (a.W + kSeg - 1) / kSeg;
     const int64_t tpi = static_cast<int64_t>(a.H) * nseg;
@@ -537,12 +628,18 @@ svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
     if (a.dbias) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, a.dbias,
                                     static_cast<int64_t>(a.B) * 3);
     const int grid = a.B * P.gpi;
-#define SVDLUT_BWD(IO, MT)                                                                      \
+#define SVDLUT_BWD_L(IO, MT, LS)                                                                \
     do {                                                                                        \
         if (P.fast_map)                                                                         \
-            hipLaunchKernelGGL((apply_bwd_kernel<IO, MT, true>), dim3(grid), dim3(block), lds, st, P); \
+            hipLaunchKernelGGL((apply_bwd_kernel<IO, MT, true, LS>), dim3(grid), dim3(block), lds, st, P); \
         else                                                                                    \
-            hipLaunchKernelGGL((apply_bwd_kernel<IO, MT, false>), dim3(grid), dim3(block), lds, st, P); \
+            hipLaunchKernelGGL((apply_bwd_kernel<IO, MT, false, LS>), dim3(grid), dim3(block), lds, st, P); \
+    } while (0)
+#define SVDLUT_BWD(IO, MT)                                                                      \
+    do {                                                                                        \
+        if (loss == 1) SVDLUT_BWD_L(IO, MT, 1);                                                 \
+        else if (loss == 2) SVDLUT_BWD_L(IO, MT, 2);                                            \
+        else SVDLUT_BWD_L(IO, MT, 0);                                                           \
     } while (0)
     if (a.io == SVDLUT_F32) {
         if (a.map_dt == SVDLUT_F32) SVDLUT_BWD(float, float); else SVDLUT_BWD(float, __half);
@@ -550,8 +647,14 @@ svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
         if (a.map_dt == SVDLUT_F32) SVDLUT_BWD(__half, float); else SVDLUT_BWD(__half, __half);
     }
 #undef SVDLUT_BWD
+#undef SVDLUT_BWD_L
     svdlut_status stt = check_launch("apply_bwd");
     if (stt != SVDLUT_OK) return stt;
+    if (L) {
+        hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(64), 0, st, L->lpart, grid, P.inv_n, L->loss);
+        stt = check_launch("apply_loss_bwd");
+        if (stt != SVDLUT_OK) return stt;
+    }
     if (P.want_dT) {
         const size_t lds2 = sizeof(float) * (static_cast<size_t>(a.D) * a.D + 3 * static_cast<size_t>(a.D) * a.R);
         hipLaunchKernelGGL(factor_grad_kernel, dim3(a.B * 9), dim3(256), lds2, st, a.dT, P.gpi,
@@ -561,4 +664,60 @@ svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) {
     return stt;
 }
 
+svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st) { return launch_bwd_impl(a, nullptr, st); }
+
 }  // namespace svdlut
+
+using namespace svdlut;
+
+namespace {
+
+size_t loss_bwd_ws_bytes(int B, int D) {
+    return ((bwd_workspace_bytes(B, D) + 255) & ~static_cast<size_t>(255)) +
+           sizeof(float) * static_cast<size_t>(B) * bwd_groups_per_image(B);
+}
+
+bool dim_ok(int32_t v) { return v >= 1 && v <= kMaxDim; }
+
+}  // namespace
+
+extern "C" {
+
+size_t svdlut_apply_loss_bwd_workspace_size(int32_t B, int32_t D) {
+    if (B < 1 || D < 2 || D > kMaxD) return 0;
+    return loss_bwd_ws_bytes(B, D);
+}
+
+svdlut_status svdlut_apply_loss_bwd(const void* x, const void* target, svdlut_dtype io, const float* U,
+                                    const float* s, const float* V, const void* map, svdlut_dtype map_dt,
+                                    const float* bias, svdlut_loss_kind kind, float* loss, void* dx, float* dU,
+                                    float* ds, float* dV, float* dmap, float* dbias, int32_t B, int32_t H,
+                                    int32_t W, int32_t h, int32_t w, int32_t D, int32_t R, void* ws,
+                                    size_t ws_bytes, hipStream_t stream) {
+    if (!x || !target || !U || !s || !V || !map || !loss || !ws)
+        return fail(SVDLUT_EINVAL, "apply_loss_bwd: null pointer");
+    if (kind != SVDLUT_LOSS_L1 && kind != SVDLUT_LOSS_MSE) return fail(SVDLUT_EINVAL, "apply_loss_bwd: kind");
+    const int nfac = (dU != nullptr) + (ds != nullptr) + (dV != nullptr);
+    if (nfac != 0 && nfac != 3) return fail(SVDLUT_EINVAL, "apply_loss_bwd: dU, ds, dV must be all set or all NULL");
+    if ((io != SVDLUT_F32 && io != SVDLUT_F16) || (map_dt != SVDLUT_F32 && map_dt != SVDLUT_F16))
+        return fail(SVDLUT_EUNSUPPORTED, "apply_loss_bwd: dtype");
+    if (B < 1) return fail(SVDLUT_EINVAL, "apply_loss_bwd: B must be >= 1");
+    if (!dim_ok(H) || !dim_ok(W) || !dim_ok(h) || !dim_ok(w))
+        return fail(SVDLUT_EINVAL, "apply_loss_bwd: H, W, h, w must be in [1, 65535]");
+    if (D < 2 || D > kMaxD || R < 1 || R > kMaxR) return fail(SVDLUT_EINVAL, "apply_loss_bwd: D or R out of range");
+    if (ws_bytes < loss_bwd_ws_bytes(B, D))
+        return fail(SVDLUT_EINVAL, "apply_loss_bwd: workspace smaller than svdlut_apply_loss_bwd_workspace_size()");
+    BwdLaunch a{};
+    a.x = x; a.dy = target; a.U = U; a.s = s; a.V = V; a.map = map;
+    a.dx = dx; a.dU = dU; a.ds = ds; a.dV = dV; a.dmap = dmap; a.dbias = dbias;
+    a.dT = static_cast<float*>(ws);
+    a.B = B; a.H = H; a.W = W; a.h = h; a.w = w; a.D = D; a.R = R;
+    a.io = io; a.map_dt = map_dt;
+    LossArgs L{kind == SVDLUT_LOSS_L1 ? 1 : 2, bias,
+               reinterpret_cast<float*>(static_cast<char*>(ws) +
+                                        ((bwd_workspace_bytes(B, D) + 255) & ~static_cast<size_t>(255))),
+               loss};
+    return launch_bwd_impl(a, &L, stream);
+}
+
+}  // extern "C"

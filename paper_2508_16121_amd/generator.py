@@ -13,7 +13,7 @@ import torch
 
 from . import _lib
 from ._lib import check
-from .ops import _DT, _need, _ptr, _stream, apply, apply_bwd, bwd_workspace, loss
+from .ops import _DT, _need, _ptr, _stream, apply, apply_bwd, apply_loss_bwd, bwd_workspace, loss, loss_bwd_workspace
 
 CONV_CH = (3, 16, 32, 64, 128, 128)
 HEAD_IN = 64
@@ -152,8 +152,9 @@ class Generator:
 
 
 class Trainer:
-    """One training step = generator forward, apply, MSE loss, apply backward (factors and
-    map only), generator backward and Adam, all on the current stream with no host sync."""
+    """One training step = generator forward, the transform's forward + MSE + backward in one
+    fused pass (factors and map gradients), generator backward and Adam, all on the current
+    stream with no host sync."""
 
     def __init__(self, gen: Generator, lr=1e-4):
         self.gen = gen
@@ -162,15 +163,15 @@ class Trainer:
 
     def step(self, x, target):
         U, s, V, m = self.gen.forward(x)
-        y = apply(x, U, s, V, m)
-        lval, dy = loss(y, target, "mse")
         B = x.shape[0]
         if B not in self._bws:
-            self._bws[B] = bwd_workspace(B, self.gen.D, x.device)
-        r = apply_bwd(x, dy, U, s, V, m, need_dx=False, need_factors=True, need_map=True, ws=self._bws[B])
+            self._bws[B] = loss_bwd_workspace(B, self.gen.D, x.device)
+        # forward, MSE and backward of the transform in one fused pass
+        r = apply_loss_bwd(x, target, U, s, V, m, kind="mse", need_dx=False, need_factors=True, need_map=True,
+                           ws=self._bws[B])
         self.gen.backward(r["dU"], r["ds"], r["dV"], r["dmap"])
         self.opt.step(self.gen.grads)
-        return lval
+        return r["loss"]
 
     def state_dict(self):
         return {"params": self.gen.params.detach().cpu().numpy(), "m": self.opt.m.cpu().numpy(),

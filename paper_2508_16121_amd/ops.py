@@ -161,6 +161,49 @@ def apply_bwd(x, dy, U, s, V, smap, need_dx=True, need_factors=True, need_map=Tr
     return out
 
 
+def loss_bwd_workspace(B, D, device):
+    n = _lib.load().svdlut_apply_loss_bwd_workspace_size(B, D)
+    return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)
+
+
+def apply_loss_bwd(x, target, U, s, V, smap, bias=None, kind="l1", need_dx=True, need_factors=True,
+                   need_map=True, need_bias=False, ws=None):
+    """Forward, loss and backward in one pass (svdlut_apply_loss_bwd): returns a dict with
+    "loss" (float32 [1]) and the requested gradients (dx, dU, ds, dV, dmap, db)."""
+    _need(x, "x", (torch.float32, torch.float16), 4)
+    _need(target, "target", (x.dtype,), 4)
+    if target.shape != x.shape:
+        raise ValueError("target must have the shape of x")
+    B, _, H, W = x.shape
+    D, R = _factors(U, s, V, B)
+    _need(smap, "smap", (torch.float32, torch.float16), 4)
+    h, w = smap.shape[2], smap.shape[3]
+    if bias is not None:
+        _need(bias, "bias")
+        if bias.shape != (B, 3):
+            raise ValueError("bias must be [B][3]")
+    dev = x.device
+    f32 = dict(device=dev, dtype=torch.float32)
+    out = {"loss": torch.empty(1, **f32)}
+    if need_dx:
+        out["dx"] = torch.empty_like(x)
+    if need_factors:
+        out["dU"], out["ds"], out["dV"] = torch.empty_like(U), torch.empty_like(s), torch.empty_like(V)
+    if need_map:
+        out["dmap"] = torch.empty(B, 9, h, w, **f32)
+    if need_bias:
+        out["db"] = torch.empty(B, 3, **f32)
+    if ws is None:
+        ws = loss_bwd_workspace(B, D, dev)
+    k = {"l1": _lib.LOSS_L1, "mse": _lib.LOSS_MSE}[kind]
+    check(_lib.load().svdlut_apply_loss_bwd(
+        _ptr(x), _ptr(target), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap), _DT[smap.dtype], _ptr(bias), k,
+        _ptr(out["loss"]), _ptr(out.get("dx")), _ptr(out.get("dU")), _ptr(out.get("ds")), _ptr(out.get("dV")),
+        _ptr(out.get("dmap")), _ptr(out.get("db")), B, H, W, h, w, D, R, _ptr(ws), ws.numel() * ws.element_size(),
+        _stream()), "svdlut_apply_loss_bwd")
+    return out
+
+
 def apply_grid_bwd(x, dy, U, s, V, smap, grids, gw, need_dx=True, need_factors=True, need_map=True,
                    need_bias=False, need_grids=True, ws=None):
     """Gradients through svdlut_apply_grid (svdlut_apply_grid_bwd); returns a dict of the

@@ -116,6 +116,26 @@ def test_validation_happens_before_any_hip_call(lib):
     assert lib.svdlut_generator_bwd(fake, null, fake, fake, fake, fake, 1, 33, 8, fake, 1 << 30, null) == 1
 
 
+def test_apply_loss_bwd_validation(lib):
+    null = None
+    fake = C.c_void_p(0x1000)
+    big = 1 << 30
+
+    def call(x=fake, t=fake, io=0, kind=0, loss=fake, dU=fake, B=1, D=33, ws=fake, wsb=big):
+        return lib.svdlut_apply_loss_bwd(x, t, io, fake, fake, fake, fake, 0, null, kind, loss, null, dU, fake,
+                                         fake, null, null, B, 8, 8, 2, 2, D, 8, ws, wsb, null)
+    assert call(t=null) == 1 and "null" in _err(lib)
+    assert call(loss=null) == 1
+    assert call(kind=5) == 1
+    assert call(dU=null) == 1 and "all set" in _err(lib)
+    assert call(io=9) == 2
+    assert call(B=0) == 1
+    assert call(D=41) == 1
+    assert call(wsb=16) == 1 and "workspace" in _err(lib)
+    assert lib.svdlut_apply_loss_bwd_workspace_size(16, 33) > lib.svdlut_apply_bwd_workspace_size(16, 33)
+    assert lib.svdlut_apply_loss_bwd_workspace_size(0, 33) == 0
+
+
 def test_lut_dims_validation(lib):
     null = None
     fake = C.c_void_p(0x1000)

@@ -111,6 +111,65 @@ def test_loss_kernels_fp16_and_unaligned(svd):
         assert np.abs(host(dy) - rdy).max() <= 2e-3 * np.abs(rdy).max()
 
 
+@pytest.mark.parametrize("kind,io,shape,with_bias", [("l1", torch.float32, (2, 37, 70, 17, 4, 6, 9), True),
+                                                      ("mse", torch.float32, (3, 64, 300, 33, 8, 8, 38), False),
+                                                      ("mse", torch.float32, (1, 21, 513, 33, 8, 3, 65), True),
+                                                      ("l1", torch.float16, (2, 40, 128, 33, 8, 5, 16), True)])
+def test_fused_loss_backward_matches_separate_passes(svd, kind, io, shape, with_bias):
+    """svdlut_apply_loss_bwd against svdlut_apply + svdlut_loss + svdlut_apply_bwd on the same
+    inputs: the loss to float rounding, the gradients to the fixed-point bar (fp32) or to the
+    fp16 rounding of the separately stored dL/dY (fp16)."""
+    B, H, W, D, R, h, w = shape
+    c = synth.single(sum(shape), H, W, D, R, h, w)
+    g = np.random.default_rng(sum(shape) + 1)
+    x = np.concatenate([c.x] * B).astype(np.float32)
+    x += g.normal(0, 0.02, x.shape).astype(np.float32) * (np.arange(B)[:, None, None, None] > 0)
+    tgt = np.clip(x + g.normal(0, 0.1, x.shape), -0.05, 1.05).astype(np.float32)
+    U, s_, V, m = (np.concatenate([a] * B) for a in (c.U, c.s, c.V, c.smap))
+    bias = g.normal(0, 0.1, (B, 3)).astype(np.float32) if with_bias else None
+    dx_, tg = dev(x, io), dev(tgt, io)
+    Ud, sd, Vd, md = dev(U), dev(s_), dev(V), dev(m)
+    bd = dev(bias) if with_bias else None
+    f = svd.apply_loss_bwd(dx_, tg, Ud, sd, Vd, md, bias=bd, kind=kind, need_bias=True)
+    y = svd.apply(dx_, Ud, sd, Vd, md, bias=bd)
+    lv, dy = svd.loss(y, tg, kind)
+    r = svd.apply_bwd(dx_, dy, Ud, sd, Vd, md, need_bias=True)
+    assert abs(host(f["loss"])[0] - host(lv)[0]) <= 2e-6 * abs(host(lv)[0])
+    # L1 kinks: where |Y - t| is at rounding level the two paths may take different signs; dx
+    # is compared away from them (the accumulated gradients absorb a single pixel)
+    yh, th = host(y), host(tg)
+    off_kink = np.abs(yh - th) > 1e-5 if kind == "l1" else np.ones(yh.shape, bool)
+    tol = 1e-4 if io == torch.float32 else 3e-3
+    for k in ("dU", "ds", "dV", "dmap", "db"):
+        close(host(f[k]), host(r[k]), tol, k)
+    close(host(f["dx"]) * off_kink, host(r["dx"]) * off_kink, tol, "dx")
+    # and the loss and gradients against the fp64 oracle (fp32 storage only: dL/dY from the oracle's own Y)
+    if io == torch.float32:
+        ry = ol.apply(x, U, s_, V, m, bias)
+        rl, G = (ol.l1_loss if kind == "l1" else ol.mse_loss)(ry, tgt)
+        assert abs(host(f["loss"])[0] - rl) <= 1e-5 * abs(rl)
+        ref = ol.apply_bwd(x, U, s_, V, m, G)
+        for k in ("dU", "ds", "dV", "dmap"):
+            close(host(f[k]), ref[k], 1e-4, k)
+        ok = off_kink & ((np.abs(ry - tgt) > 1e-5) if kind == "l1" else True)
+        close(host(f["dx"]) * ok, ref["dx"] * ok, 1e-4, "dx")
+
+
+def test_fused_loss_backward_nonfinite_and_reproducible(svd):
+    c = synth.single(77, 32, 96, 17, 4, 4, 12)
+    x, U, s_, V, m = (dev(a) for a in (c.x, c.U, c.s, c.V, c.smap))
+    t = torch.rand_like(x)
+    a = svd.apply_loss_bwd(x, t, U, s_, V, m, kind="mse")
+    b = svd.apply_loss_bwd(x, t, U, s_, V, m, kind="mse")
+    for k in a:
+        assert torch.equal(a[k], b[k]), k
+    t[0, 1, 3, 5] = float("nan")
+    r = svd.apply_loss_bwd(x, t, U, s_, V, m, kind="mse")
+    assert torch.isnan(r["loss"]).all() and torch.isnan(r["dU"]).any()
+    r = svd.apply_loss_bwd(x, t, U, s_, V, m, kind="l1")           # sign(NaN) = 0, as in svdlut_loss
+    assert torch.isnan(r["loss"]).all() and torch.isfinite(r["dU"]).all()
+
+
 def test_autograd_matches_apply_bwd(svd):
     c = synth.single(41, 40, 72, 17, 4, 5, 9)
     x, U, s, V, m = (dev(a).requires_grad_() for a in (c.x, c.U, c.s, c.V, c.smap))
