@@ -69,6 +69,20 @@ def test_generator_forward_parity(svd, G, hw):
         rel_close(host(a), b, 2e-2, k)
 
 
+def test_generator_forward_parity_4k_frames(svd, G):
+    """The inference configuration's frame size (3x2160x3840, two frames of the batch): the
+    downsample from 4K is the only size-dependent step."""
+    D, R = 33, 8
+    P = random_params(D, R, 21)
+    g = np.random.default_rng(22)
+    x = g.uniform(0, 1, (2, 3, 2160, 3840)).astype(np.float32)
+    gen = G.Generator(D, R, params=og.flatten(P, D, R).astype(np.float32))
+    U, s, V, m = gen.forward(torch.from_numpy(x).cuda())
+    rU, rs, rV, rm, _ = og.forward(P, x, D, R, mixed=True)
+    for a, b, k in ((U, rU, "U"), (s, rs, "s"), (V, rV, "V"), (m, rm, "map")):
+        rel_close(host(a), b, 2e-2, k)
+
+
 def test_generator_backward_parity(svd, G):
     D, R = 33, 8
     P = random_params(D, R, 3)

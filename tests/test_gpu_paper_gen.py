@@ -88,6 +88,18 @@ def test_paper_generator_forward_parity(PM, K, hw, use_mask):
         rel_close(got[k], ref[k], 2e-2, k)
 
 
+def test_paper_generator_forward_parity_4k_frame(PM):
+    """A 3x2160x3840 input: the downsample from 4K is the only size-dependent step."""
+    K = 6
+    P = rand_params(150, K)
+    x = np.random.default_rng(151).uniform(0, 1, (1, 3, 2160, 3840)).astype(np.float32)
+    gen = PM.PaperGenerator(D, R, K, Ds, params=pg.flatten(P, D, R, K, Ds).astype(np.float32))
+    got = gpu_out_to_oracle_keys(gen.forward(torch.from_numpy(x).cuda()))
+    ref, _ = pg.forward(P, x, D, R, K, Ds, mixed=True)
+    for k in ref:
+        rel_close(got[k], ref[k], 2e-2, k)
+
+
 @pytest.mark.parametrize("K,use_mask", [(6, True), (0, False)])
 def test_paper_generator_backward_parity(PM, K, use_mask):
     """Parameter gradients vs the bf16-mirror oracle.  The mirror cannot take every bf16
