@@ -180,3 +180,25 @@ def test_unfused_original_structure_parity(svd, shape):
     ref = np.stack([ou.original_structure(x[b], gr[b], gw[b], gb[b], Wf[b], bf[b], T3[b])[0] for b in range(B)])
     err = np.abs(y - ref).max()
     assert err <= TOL32, f"max-abs {err}"
+
+
+def test_unfused_original_structure_4k_sampled(svd):
+    """The unfused baseline on a full 4K frame (the benchmark's shape), checked at sampled
+    pixels: f_s at those pixels from the slicing oracle, the 1x1 fusion, the float32 fused
+    colours and the 3D-LUT oracle."""
+    from oracle import grid as og
+    from oracle import unfused as ou
+    g = np.random.default_rng(4096)
+    B, H, W, K, Ds, D = 1, 2160, 3840, 6, 17, 33
+    x, gr, gw, gb, Wf, bf, T3 = _unfused_inputs(g, B, H, W, K, Ds, D)
+    say("unfused 4K")
+    y = svd.unfused_apply(*(dev(a) for a in (x, gr, gw, gb, Wf, bf, T3)))
+    ys = np.concatenate([g.integers(0, H, 3000), [0, H - 1, 0, H - 1]])
+    xs = np.concatenate([g.integers(0, W, 3000), [0, W - 1, W - 1, 0]])
+    got = host(y)[0][:, ys, xs]
+    fs = og.slice_grids_at(x[0], gr[0], gw[0], gb[0], ys, xs)                   # [K][n]
+    inp = np.concatenate([x[0][:, ys, xs].astype(np.float64), fs])              # [3 + K][n]
+    xbar = (Wf[0].astype(np.float64) @ inp + bf[0][:, None]).astype(np.float32)
+    ref = ou.lut3d(xbar[:, None, :], T3[0])[:, 0, :]
+    err = np.abs(got - ref).max()
+    assert err <= TOL32, f"max-abs {err}"
