@@ -12,6 +12,11 @@
 // written as float partials and summed in a fixed order by a second kernel.  The xy plane's
 // contributions of a lane's four pixels are summed in registers first (they share the tile
 // row and at most three x vertices), since all lanes of a wave hit the same few vertices.
+// The xc and yc planes receive one term per pixel; neighbouring pixels have similar colours,
+// so many lanes of a wave add to the same entry (the yc plane's row is the tile's, so up to
+// the whole wave).  Those atomics go to ncx / ncy replicas of the planes selected by the lane
+// index, which divides the same-address serialisation; the replicas are added in a fixed
+// order before the partials are written (integer sums, so the result does not change).
 #include "bwd_common.h"
 
 #include <algorithm>
@@ -30,14 +35,15 @@ struct GridBwdDev {
     int B, H, W, K, Ds, gpi;
     int64_t per;              // row segments per workgroup
     int want_g;
+    int ncx, ncy;             // replicas of the xc / yc adjoint planes (powers of two)
 };
 
 __device__ __forceinline__ int part_floats(int Ds) { return 9 * Ds * Ds + 3; }
 
 template <typename IO, bool VEC>
 __device__ __forceinline__ void grid_bwd_tile(const GridBwdDev& P, int b, int y, int seg, const float* Cl,
-                                              int* Al, int Dsp, const AxisMap& gax, int iy, float wy,
-                                              float sc, float (&gsum)[3]) {
+                                              int* Al, int* Ayr, int* Axr, int Dsp, const AxisMap& gax, int iy,
+                                              float wy, float sc, float (&gsum)[3]) {
     const int lane = threadIdx.x & (kWave - 1);
     const int W = P.W, Ds = P.Ds;
     const int xs = seg * kSeg;
@@ -92,8 +98,8 @@ __device__ __forceinline__ void grid_bwd_tile(const GridBwdDev& P, int b, int y,
             // xc and yc planes
             if (P.want_g) {
                 const float gs = G * sc;
-                int* Axc = Al + (3 * c + 1) * PL + ixk * Dsp + ic;
-                int* Ayc = Al + (3 * c + 2) * PL + iy * Dsp + ic;
+                int* Axc = Axr + (c * P.ncx + (lane & (P.ncx - 1))) * PL + ixk * Dsp + ic;
+                int* Ayc = Ayr + (c * P.ncy + (lane & (P.ncy - 1))) * PL + iy * Dsp + ic;
                 const float wc0 = gs * (1.f - wc), wc1 = gs * wc;
                 lds_addi(Axc, fix_mul(wc0, 1.f - wx));
                 lds_addi(Axc + 1, fix_mul(wc1, 1.f - wx));
@@ -146,7 +152,9 @@ __global__ void __launch_bounds__(512) grid_bwd_kernel(GridBwdDev P) {
     const int Ds = P.Ds, Dsp = grid_plane_stride(Ds), PL = Ds * Dsp;
     float* Cl = smem;                                   // combined planes [3 c][3 planes][Ds][Dsp]
     int* Al = reinterpret_cast<int*>(Cl + 9 * PL);      // their adjoints, int32 fixed point
-    float* red = reinterpret_cast<float*>(Al + 9 * PL); // one float per wave
+    int* Ayr = Al + 9 * PL;                             // yc replicas [3 c][ncy][Ds][Dsp]
+    int* Axr = Ayr + 3 * P.ncy * PL;                    // xc replicas [3 c][ncx][Ds][Dsp]
+    float* red = reinterpret_cast<float*>(Axr + 3 * P.ncx * PL); // one float per wave
     const int nw = blockDim.x / kWave;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     const int b = blockIdx.x / P.gpi;
@@ -169,7 +177,7 @@ __global__ void __launch_bounds__(512) grid_bwd_kernel(GridBwdDev P) {
             v = fmaf(wsrc[3 * kk + pl], gsrc[(static_cast<size_t>(kk) * 3 + pl) * Ds * Ds + r], v);
         Cl[cp * PL + i * Dsp + jj] = v;
     }
-    for (int e = threadIdx.x; e < 9 * PL; e += blockDim.x) Al[e] = 0;
+    for (int e = threadIdx.x; e < (9 + 3 * (P.ncy + P.ncx)) * PL; e += blockDim.x) Al[e] = 0;
 
     // fixed-point scale from the band's max |dy|
     const int64_t plane = static_cast<int64_t>(P.H) * P.W;
@@ -199,12 +207,22 @@ __global__ void __launch_bounds__(512) grid_bwd_kernel(GridBwdDev P) {
         axis_left(gay, y, iy, ry);
         const float wy = static_cast<float>(ry) * gay.inv;
         if (base_ok && seg * kSeg + kSeg <= P.W)
-            grid_bwd_tile<IO, true>(P, b, y, seg, Cl, Al, Dsp, gax, iy, wy, sc, gsum);
+            grid_bwd_tile<IO, true>(P, b, y, seg, Cl, Al, Ayr, Axr, Dsp, gax, iy, wy, sc, gsum);
         else
-            grid_bwd_tile<IO, false>(P, b, y, seg, Cl, Al, Dsp, gax, iy, wy, sc, gsum);
+            grid_bwd_tile<IO, false>(P, b, y, seg, Cl, Al, Ayr, Axr, Dsp, gax, iy, wy, sc, gsum);
     }
     __syncthreads();
     if (!P.want_g) return;
+    // fold the replicas into the xc and yc planes (fixed order)
+    for (int e = threadIdx.x; e < 3 * PL; e += blockDim.x) {
+        const int c = e / PL, r = e - c * PL;
+        int sy = 0, sx = 0;
+        for (int q = 0; q < P.ncy; ++q) sy += Ayr[(c * P.ncy + q) * PL + r];
+        for (int q = 0; q < P.ncx; ++q) sx += Axr[(c * P.ncx + q) * PL + r];
+        Al[(3 * c + 2) * PL + r] = sy;
+        Al[(3 * c + 1) * PL + r] = sx;
+    }
+    __syncthreads();
     float* out = P.part + (static_cast<size_t>(b) * P.gpi + j) * part_floats(Ds);
     const float isc = bad ? __builtin_nanf("") : 1.f / sc;
     for (int e = threadIdx.x; e < 9 * Ds * Ds; e += blockDim.x) {
@@ -287,7 +305,19 @@ svdlut_status launch_grid_bwd(const GridBwdLaunch& a, hipStream_t st) {
     P.want_g = a.dgrids != nullptr;
     if (!P.dx && !P.want_g) return SVDLUT_OK;
     const int block = 512;
-    const size_t lds = sizeof(float) * (2 * static_cast<size_t>(grid_floats(a.Ds)) + block / kWave);
+    // as many replicas as the LDS allows: 8 / 4 at Ds = 17, fewer for larger grids
+    const size_t PL = static_cast<size_t>(a.Ds) * grid_plane_stride(a.Ds);
+    const size_t lds_cap = static_cast<size_t>(device_info().lds_per_block);
+    auto lds_of = [&](int ny, int nx) {
+        return sizeof(float) * (2 * static_cast<size_t>(grid_floats(a.Ds)) + 3 * (ny + nx) * PL + block / kWave);
+    };
+    P.ncy = 8;
+    P.ncx = 4;
+    while ((P.ncy > 1 || P.ncx > 1) && lds_of(P.ncy, P.ncx) > lds_cap) {
+        if (P.ncy >= 2 * P.ncx || P.ncx == 1) P.ncy /= 2;
+        else P.ncx /= 2;
+    }
+    const size_t lds = lds_of(P.ncy, P.ncx);
     const int grid = a.B * P.gpi;
     if (a.io == SVDLUT_F32)
         hipLaunchKernelGGL(grid_bwd_kernel<float>, dim3(grid), dim3(block), lds, st, P);
