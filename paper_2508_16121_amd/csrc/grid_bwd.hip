@@ -305,14 +305,14 @@ svdlut_status launch_grid_bwd(const GridBwdLaunch& a, hipStream_t st) {
     P.want_g = a.dgrids != nullptr;
     if (!P.dx && !P.want_g) return SVDLUT_OK;
     const int block = 512;
-    // as many replicas as the LDS allows: 8 / 4 at Ds = 17, fewer for larger grids
+    // as many replicas as the LDS allows: 16 / 8 at Ds = 17, fewer for larger grids
     const size_t PL = static_cast<size_t>(a.Ds) * grid_plane_stride(a.Ds);
     const size_t lds_cap = static_cast<size_t>(device_info().lds_per_block);
     auto lds_of = [&](int ny, int nx) {
         return sizeof(float) * (2 * static_cast<size_t>(grid_floats(a.Ds)) + 3 * (ny + nx) * PL + block / kWave);
     };
-    P.ncy = 8;
-    P.ncx = 4;
+    P.ncy = 16;
+    P.ncx = 8;
     while ((P.ncy > 1 || P.ncx > 1) && lds_of(P.ncy, P.ncx) > lds_cap) {
         if (P.ncy >= 2 * P.ncx || P.ncx == 1) P.ncy /= 2;
         else P.ncx /= 2;
