@@ -47,7 +47,10 @@ __device__ __forceinline__ void grid_bwd_tile(const GridBwdDev& P, int b, int y,
     const int lane = threadIdx.x & (kWave - 1);
     const int W = P.W, Ds = P.Ds;
     const int xs = seg * kSeg;
-    const int x0 = xs + lane * kPxPerLane;
+    // lane -> 4-pixel block of the segment by a fixed permutation (stride 17 of 64): lanes of
+    // one instruction then sit far apart along the row, with less similar colours, so their
+    // LDS atomics meet the same address less often
+    const int x0 = xs + ((lane * 17) & (kWave - 1)) * kPxPerLane;
     if (x0 >= W) return;
     const int64_t plane = static_cast<int64_t>(P.H) * W;
     const int64_t img = static_cast<int64_t>(b) * 3 * plane + static_cast<int64_t>(y) * W;

@@ -67,7 +67,10 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
     const int H = a.H, W = a.W, h = a.h, w = a.w, D = a.D;
     (void)H;
     const int xs = seg * kSeg;
-    const int x0 = xs + lane * kPxPerLane;
+    // lane -> 4-pixel block of the segment by a fixed permutation (stride 17 of 64): lanes of
+    // one instruction then sit far apart along the row, with less similar colours, so their
+    // LDS atomics meet the same address less often
+    const int x0 = xs + ((lane * 17) & (kWave - 1)) * kPxPerLane;
     const int xlast = min(xs + kSeg, W) - 1;
     const int64_t plane = G.plane;
     const int64_t img = static_cast<int64_t>(b) * 3 * plane + static_cast<int64_t>(y) * W;
