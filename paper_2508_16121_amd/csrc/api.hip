@@ -76,20 +76,21 @@ static svdlut_status check_dtype(svdlut_dtype t, const char* what) {
         if (st_ != SVDLUT_OK) return st_;         \
     } while (0)
 
-// Default launch shape of the fused apply: one 1024-thread workgroup per CU (16 waves, the
-// most the kernel's register budget allows) when its LDS fits, else the largest that fits.
-static int default_block(int D, int R, int ncol_max, const DeviceInfo& di, int Ds = 0) {
+// Default launch shape of the fused apply: one workgroup of the variant's largest size per CU
+// (maxb = 1024: 16 waves, the most a 128-VGPR budget allows; 512 for the variants built with
+// 256 VGPRs) when its LDS fits, else the largest that fits.
+static int default_block(int D, int R, int ncol_max, const DeviceInfo& di, int Ds = 0, int maxb = 1024) {
     for (int b : {1024, 512, 256, 128, 64})
-        if (apply_lds_bytes(D, R, b, ncol_max, Ds) <= static_cast<size_t>(di.lds_per_block)) return b;
+        if (b <= maxb && apply_lds_bytes(D, R, b, ncol_max, Ds) <= static_cast<size_t>(di.lds_per_block)) return b;
     return 0;
 }
 
-// Workgroups per CU that can be resident: the kernel holds up to 128 VGPRs per lane, so a CU
-// fits 16 of its waves (4 per SIMD); LDS may allow fewer.
-static int blocks_per_cu(int D, int R, int block, int ncol_max, const DeviceInfo& di, int Ds = 0) {
+// Workgroups per CU that can be resident: a variant built for maxb threads per workgroup
+// holds 65536 / maxb VGPRs per lane, so a CU fits maxb / 64 of its waves; LDS may allow fewer.
+static int blocks_per_cu(int D, int R, int block, int ncol_max, const DeviceInfo& di, int Ds = 0, int maxb = 1024) {
     const size_t lds = apply_lds_bytes(D, R, block, ncol_max, Ds);
     const int by_lds = static_cast<int>(di.lds_per_cu / std::max<size_t>(lds, 1));
-    const int by_waves = 16 / std::max(block / kWave, 1);
+    const int by_waves = maxb / std::max(block, kWave);
     return std::max(1, std::min(by_lds, by_waves));
 }
 
@@ -135,12 +136,13 @@ static svdlut_status apply_impl(const void* x, void* y, svdlut_dtype io, const f
     a.fast_map = map_fast_ok(W, w) ? 1 : 0;
     a.grids = grids; a.gw = gw; a.gb = gb; a.K = K; a.Ds = Ds;
     const int lds_ds = K > 0 ? Ds : 0;
-    a.block = default_block(D, R, a.ncol_max, di, lds_ds);
+    const int maxb = apply_max_block(io, a.fast_map != 0, K > 0);
+    a.block = default_block(D, R, a.ncol_max, di, lds_ds, maxb);
     if (a.block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply: map too wide for LDS staging");
     // small frames: narrower workgroups, so that the tiles (one per wave at least) spread over
     // every CU instead of filling a few 16-wave workgroups
     while (a.block > kWave && a.total_tiles < static_cast<int64_t>(di.cus) * (a.block / kWave)) a.block /= 2;
-    const int64_t max_grid = static_cast<int64_t>(di.cus) * blocks_per_cu(D, R, a.block, a.ncol_max, di, lds_ds);
+    const int64_t max_grid = static_cast<int64_t>(di.cus) * blocks_per_cu(D, R, a.block, a.ncol_max, di, lds_ds, maxb);
     const int64_t tiles_per_block_min = a.block / kWave;   // at least one tile per wave
     a.grid = static_cast<int>(std::max<int64_t>(1, std::min(max_grid, (a.total_tiles + tiles_per_block_min - 1) / tiles_per_block_min)));
     a.io = io; a.map_dt = map_dt;
@@ -473,22 +475,24 @@ svdlut_status svdlut_plan_create(const svdlut_image_desc* descs, int32_t B, int3
     const DeviceInfo& di = device_info();
     p->device = di.device;
     const std::string key = tune_key(p, di);
+    const int maxb = apply_max_block(io, p->fast_map != 0, false);
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
-        if (it != g_tune.end() && apply_lds_bytes(D, R, it->second.first, p->ncol_max) <= static_cast<size_t>(di.lds_per_block)) {
+        if (it != g_tune.end() && it->second.first <= maxb &&
+            apply_lds_bytes(D, R, it->second.first, p->ncol_max) <= static_cast<size_t>(di.lds_per_block)) {
             plan_set_shape(p, it->second.first, it->second.second, di);
             p->tuned = 1;
         }
     }
     if (!p->tuned) {
-        const int blk = default_block(D, R, p->ncol_max, di);
+        const int blk = default_block(D, R, p->ncol_max, di, 0, maxb);
         if (blk == 0) {
             delete p;
             return fail(SVDLUT_EUNSUPPORTED, "plan_create: map too wide for LDS staging");
         }
-        plan_set_shape(p, blk, blocks_per_cu(D, R, blk, p->ncol_max, di), di);
+        plan_set_shape(p, blk, blocks_per_cu(D, R, blk, p->ncol_max, di, 0, maxb), di);
     }
     if (hipMalloc(reinterpret_cast<void**>(&p->d_descs), sizeof(ImgGeom) * B) != hipSuccess ||
         hipMalloc(reinterpret_cast<void**>(&p->d_tiles), sizeof(int64_t) * (B + 1)) != hipSuccess) {
@@ -561,9 +565,11 @@ svdlut_status svdlut_plan_autotune(svdlut_plan* p, const void* x, void* y, const
     const DeviceInfo& di = device_info();
     struct Cand { int block, bpc; };
     std::vector<Cand> cands;
+    const int maxthr = apply_max_block(p->io, p->fast_map != 0, false);
     for (int blk : {256, 512, 1024}) {
+        if (blk > maxthr) continue;
         if (apply_lds_bytes(p->D, p->R, blk, p->ncol_max) > static_cast<size_t>(di.lds_per_block)) continue;
-        const int maxb = blocks_per_cu(p->D, p->R, blk, p->ncol_max, di);
+        const int maxb = blocks_per_cu(p->D, p->R, blk, p->ncol_max, di, 0, maxthr);
         for (int bpc = 1; bpc <= maxb; bpc *= 2) cands.push_back({blk, bpc});
         if (maxb & (maxb - 1)) cands.push_back({blk, maxb});
     }

@@ -73,6 +73,7 @@ __host__ __device__ inline int grid_plane_stride(int Ds) { return Ds | 1; }
 __host__ __device__ inline int grid_floats(int Ds) { return 9 * Ds * grid_plane_stride(Ds); }
 
 size_t apply_lds_bytes(int D, int R, int block, int ncol_max, int Ds = 0);
+int apply_max_block(svdlut_dtype io, bool fast_map, bool grid);
 int map_cols_bound(int W, int w);
 bool map_fast_ok(int W, int w);
 svdlut_status launch_apply(const ApplyLaunch& a, hipStream_t st);

@@ -411,9 +411,20 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
     }
 }
 
+// Largest workgroup an instantiation is compiled for.  Half-precision I/O with grid slicing
+// or with per-pixel map columns needs more than the 128 VGPRs per lane that a 1024-thread
+// workgroup leaves (it spilled to scratch and ran 4-5x slower), so those variants are built
+// for 512 threads (up to 256 VGPRs, 8 waves per CU).
+template <typename IO, bool FASTMAP, bool GRID>
+constexpr int apply_threads() { return (sizeof(IO) == 2 && (GRID || !FASTMAP)) ? 512 : 1024; }
+
+int apply_max_block(svdlut_dtype io, bool fast_map, bool grid) {
+    return (io == SVDLUT_F16 && (grid || !fast_map)) ? 512 : 1024;
+}
+
 // Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave runs.
 template <typename IO, typename MT, bool FASTMAP, bool GRID>
-__global__ void __launch_bounds__(1024) apply_kernel(ApplyLaunch a) {
+__global__ void __launch_bounds__((apply_threads<IO, FASTMAP, GRID>())) apply_kernel(ApplyLaunch a) {
     extern __shared__ float smem[];
     const int D = a.D;
     float* Tl = smem;
@@ -484,6 +495,8 @@ static void launch_typed(const ApplyLaunch& a, size_t lds, hipStream_t st) {
 }
 
 svdlut_status launch_apply(const ApplyLaunch& a, hipStream_t st) {
+    if (a.block > apply_max_block(static_cast<svdlut_dtype>(a.io), a.fast_map != 0, a.K > 0))
+        return fail(SVDLUT_EINVAL, "apply: workgroup larger than the kernel variant allows");
     const size_t lds = apply_lds_bytes(a.D, a.R, a.block, a.ncol_max, a.K > 0 ? a.Ds : 0);
     if (a.io == SVDLUT_F32) {
         if (a.map_dt == SVDLUT_F32) launch_typed<float, float>(a, lds, st);

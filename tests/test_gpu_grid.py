@@ -72,6 +72,15 @@ def test_apply_grid_fp16_storage(svd):
            label="fp16")
 
 
+@pytest.mark.parametrize("mt", [torch.float16, torch.float32])
+def test_apply_grid_fp16_per_pixel_map(svd, mt):
+    # a map finer than a third of the image (per-pixel map columns) with half-precision
+    # I/O: the variant built for 512-thread workgroups
+    c, gr, gw, gb = synth.grid_case(43, 60, 130, 33, 8, 45, 100)
+    _check(svd, c.x, c.U, c.s, c.V, c.smap, gr, gw, gb, io=torch.float16, mt=mt, tol=TOL16,
+           label="fp16 per-pixel map")
+
+
 def test_zero_grids_equal_plain_apply(svd):
     c, gr, gw, gb = synth.grid_case(42, 64, 256, 33, 8, 8, 32)
     args = [dev(a) for a in (c.x, c.U, c.s, c.V, c.smap)]

@@ -130,6 +130,18 @@ def test_apply_fp16_storage(svd):
         _check_apply(svd, x, U, s, V, m, io=torch.float16, mt=torch.float16, tol=TOL16, label="fp16")
 
 
+def test_apply_fp16_per_pixel_map(svd):
+    # map finer than a third of the image: each pixel blends its own pair of map columns
+    # (with half-precision I/O, the variant built for 512-thread workgroups)
+    g = np.random.default_rng(12)
+    for (H, W, h, w) in [(40, 70, 30, 50), (130, 300, 100, 200)]:
+        x = synth.image(g, H, W)[None]
+        U, s, V = synth.factors(g, 1, 33, 8)
+        m = synth.spatial_map(g, 1, h, w)
+        _check_apply(svd, x, U, s, V, m, io=torch.float16, mt=torch.float16, tol=TOL16,
+                     label="fp16 per-pixel map")
+
+
 def test_apply_4k_frame_sampled(svd):
     """Full 3840x2160 frame, D=33 R=8, 270x480 map, float32: sampled rows/columns vs the oracle."""
     c = synth.frame_4k()

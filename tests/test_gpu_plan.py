@@ -105,6 +105,30 @@ def test_plan_autotune(svd, tmp_path, monkeypatch):
     oracle_check(packed, x, m, y2, 2e-3)
 
 
+def test_plan_fp16_per_pixel_maps_autotune(svd, tmp_path, monkeypatch):
+    # maps finer than a third of their images (per-pixel map columns) with half-precision
+    # I/O: default shape and every autotune candidate stay within the variant's 512 threads
+    monkeypatch.setenv("SVDLUT_TUNE_CACHE", str(tmp_path / "tune.json"))
+    g = synth.rng(990)
+    images = []
+    for (H, W, h, w) in [(40, 70, 30, 50), (64, 150, 64, 150), (96, 130, 20, 60)]:
+        x = synth.image(g, H, W)
+        U, s, V = synth.factors(g, 1, 33, 8)
+        m = synth.spatial_map(g, 1, h, w)
+        images.append((x, U[0], s[0], V[0], m[0]))
+    packed = synth.pack_uneven(images)
+    say("plan fp16 per-pixel maps")
+    plan, x, m, y, (U, s, V) = run_plan(svd, packed)
+    assert plan.info()["block"] <= 512
+    oracle_check(packed, x, m, y, 2e-3)
+    plan.autotune(x, y, U, s, V, m)
+    assert plan.info()["tuned"] == 1 and plan.info()["block"] <= 512
+    y2 = torch.zeros_like(y)
+    plan.launch(x, y2, U, s, V, m)
+    torch.cuda.synchronize()
+    oracle_check(packed, x, m, y2, 2e-3)
+
+
 def test_plan_full_uneven_batch_sampled(svd):
     """64 images of uneven size (480x640, 1080x1920, 2160x3840 bases, +-10% width jitter),
     fp16 storage, own D=33 R=8 factors and 1/8-resolution maps: one graph-replayed launch,
