@@ -317,6 +317,13 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
     store_px4<IO, VEC>(yout + 2 * plane, x0, g.W, out[2]);
 }
 
+// Largest workgroup an instantiation is compiled for.  Half-precision I/O with grid slicing
+// or with per-pixel map columns needs more than the 128 VGPRs per lane that a 1024-thread
+// workgroup leaves (it spilled to scratch and ran 4-5x slower), so those variants are built
+// for 512 threads (up to 256 VGPRs, 8 waves per CU).
+template <typename IO, bool FASTMAP, bool GRID>
+constexpr int apply_threads() { return (sizeof(IO) == 2 && (GRID || !FASTMAP)) ? 512 : 1024; }
+
 // One image's share [ta, tb) (local row-major tile indices) of a workgroup's chunk.  Inside
 // it the tiles are walked column-major (same segment, consecutive rows) in one contiguous
 // run per wave, so a wave keeps its staged raw map rows for about h/H of a map cell's
@@ -369,6 +376,13 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
         gt.Gl = Gl;
         gt.gax = make_axis(g.W, a.Ds);
     }
+    // EARLY (the variants built for 1024 threads): the first tile's pixels are requested
+    // before the LUT rebuild, so their memory latency overlaps it, and each later tile's right
+    // after the previous tile.  The 512-thread variants measured faster loading each tile's
+    // pixels at its start.
+    constexpr bool EARLY = apply_threads<IO, FASTMAP, GRID>() == 1024;
+    float px[3][4];
+    if (EARLY && k < k1) load_tile<IO, VEC>(a, g, ya + yr, seg * kSeg, px);
     const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
     stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R, min(a.R, 8));
     float bias3[3] = {0.f, 0.f, 0.f};
@@ -380,15 +394,14 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
         for (int kk = 0; kk < a.K; ++kk) bias3[kk % 3] += bsrc[kk];
     }
     const AxisMap gay = GRID ? make_axis(g.H, a.Ds) : AxisMap{};
-    // Each tile loads its pixels, stages/blends the map and computes: with 16 waves per CU
-    // the other waves cover a wave's load latency (a prefetch of the next tile measured no
-    // faster and costs registers).
+    // Each tile stages/blends the map and computes: with 16 waves per CU the other waves
+    // cover a wave's load latency (holding a second tile's pixels in registers measured no
+    // faster).
     int st_seg = -1, st_iv = -1, clo = 0, ncols = 0;
     while (k < k1) {
         const int y = ya + yr;
         const int xs = seg * kSeg;
-        float px[3][4];
-        load_tile<IO, VEC>(a, g, y, xs, px);
+        if (!EARLY) load_tile<IO, VEC>(a, g, y, xs, px);
         int iv; uint32_t remv;
         axis_left(g.ay, y, iv, remv);
         if (seg != st_seg || iv != st_iv) {
@@ -408,15 +421,9 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
         compute_tile<IO, FASTMAP, VEC, GRID>(a, g, Tl, stage, clo, D, y, xs, px, bias3, gt);
         wave_sync();   // the stage region is rewritten for the next tile
         advance(seg, yr, k);
+        if (EARLY && k < k1) load_tile<IO, VEC>(a, g, ya + yr, seg * kSeg, px);
     }
 }
-
-// Largest workgroup an instantiation is compiled for.  Half-precision I/O with grid slicing
-// or with per-pixel map columns needs more than the 128 VGPRs per lane that a 1024-thread
-// workgroup leaves (it spilled to scratch and ran 4-5x slower), so those variants are built
-// for 512 threads (up to 256 VGPRs, 8 waves per CU).
-template <typename IO, bool FASTMAP, bool GRID>
-constexpr int apply_threads() { return (sizeof(IO) == 2 && (GRID || !FASTMAP)) ? 512 : 1024; }
 
 int apply_max_block(svdlut_dtype io, bool fast_map, bool grid) {
     return (io == SVDLUT_F16 && (grid || !fast_map)) ? 512 : 1024;
