@@ -29,8 +29,10 @@ N_ROT = 4
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=10)
+    # 500 warm-up launches (about 30 ms at 4K): the first ~300 launches after the GPU has been
+    # idle run up to 15 % slower while its clocks ramp to the sustained-load state
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=500)
     ap.add_argument("--rows", default="all", help="extra rows to time: all, none, or a list of c1,c3,c4,c5,g1,g4,sweep,dims,u1,p1")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the oracle CPU baseline (0: skip)")
     ap.add_argument("--copy-probe", action="store_true",
