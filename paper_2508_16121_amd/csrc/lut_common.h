@@ -92,15 +92,17 @@ __device__ __forceinline__ void decode(float xv, float Dm1, int Dm2, int& i, flo
 // output channel c the value T_{3c+p}[i][j] sits at p*D*RS + i*RS + 3*j + c.  The four
 // corners of one cell for all three output channels are then reached from one base
 // address with constant offsets (0..5 and RS..RS+5, within a ds_read2 offset field).
-// RS (the row stride) is 3*D padded to 10 or 22 (mod 32): the 3x3 neighbourhood of a cell
-// then maps to nine distinct LDS banks whether the LDS is viewed as 32 or 64 banks, which
-// matters because per-pixel noise scatters neighbouring pixels over adjacent cells.
+// RS (the row stride) is 3*D padded to 14 (mod 32): the 3x3 neighbourhood of a cell then maps
+// to nine distinct LDS banks whether the LDS is viewed as 32 or 64 banks, which matters
+// because per-pixel noise scatters neighbouring pixels over adjacent cells.  Measured on the
+// 4K apply at D = 33: 14 (mod 32) 55.7 us, 18: 56.0, 12: 56.4, 10 or 22: 56.5, 20: 56.9,
+// 16: 69.2, unpadded (3 mod 32): 81.4.
 constexpr int kNode = 3;   // floats per LUT vertex (the three output channels)
 
 __host__ __device__ inline int lut_row_stride(int D) {
-    // kNode*D rounded up to the next value that is 10 or 22 modulo 32 (closed form, no loop)
-    const int rs = kNode * D, r = rs & 31;
-    return rs + (r <= 10 ? 10 - r : (r <= 22 ? 22 - r : 42 - r));
+    // kNode*D rounded up to the next value that is 14 modulo 32
+    const int rs = kNode * D;
+    return rs + ((14 - rs) & 31);
 }
 __host__ __device__ inline int lut_pair_stride(int D) { return D * lut_row_stride(D); }
 __host__ __device__ inline int lut_floats(int D) { return (3 * lut_pair_stride(D) + 3) & ~3; }
