@@ -17,8 +17,6 @@ constexpr int kMaxDim = 65535;
 constexpr int kWave = 64;
 constexpr int kPxPerLane = 4;                      // pixels per lane per row segment
 constexpr int kSeg = kWave * kPxPerLane;           // pixels per row segment (one wave)
-constexpr int kMapStride = 12;                     // floats per staged map column (9 used, 16-B aligned)
-constexpr int kRawStride = 24;                     // floats per raw map column: 9 top at 0, 9 diff at 12 (16-B aligned)
 
 void set_error(const std::string& msg);
 svdlut_status fail(svdlut_status st, const std::string& msg);

@@ -30,6 +30,9 @@ namespace svdlut {
 namespace {
 
 constexpr int kBwdStride = 9;   // values per staged map column in the backward
+// floats per raw map column (nine top values at 0, nine row differences at 12); odd, like
+// kBwdStride, so the ~32 columns a wave touches at once fall on distinct LDS banks
+constexpr int kBwdRawStride = 21;
 
 struct BwdDev {
     BwdLaunch a;
@@ -110,7 +113,7 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
                 v0[l] = ldf<MT>(m0 + l * mplane + j);
                 v1[l] = ldf<MT>(m0 + l * mplane + rowd + j);
             }
-            float* dst = raw + j * kRawStride;
+            float* dst = raw + j * kBwdRawStride;
 #pragma unroll
             for (int l = 0; l < 9; ++l) {
                 dst[l] = v0[l];
@@ -122,7 +125,7 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
         wave_sync();
     }
     for (int j = lane; j < ncols; j += kWave) {
-        const float* src = raw + j * kRawStride;
+        const float* src = raw + j * kBwdRawStride;
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
             stage[j * kBwdStride + l] = fmaf(dv, src[12 + l], src[l]);
@@ -327,8 +330,8 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     float* aux = reinterpret_cast<float*>(macc + ((macc_n + 3) & ~3));
     const int nw = blockDim.x / kWave;
     const int wave = threadIdx.x / kWave;
-    float* raw = aux + wave * P.ncol_max * (kRawStride + 2 * kBwdStride);
-    float* stage = raw + P.ncol_max * kRawStride;
+    float* raw = aux + wave * P.ncol_max * (kBwdRawStride + 2 * kBwdStride);
+    float* stage = raw + P.ncol_max * kBwdRawStride;
     int* dstage = reinterpret_cast<int*>(stage + P.ncol_max * kBwdStride);
 
     const int lb = logical_block(blockIdx.x, gridDim.x);
@@ -573,7 +576,7 @@ static size_t bwd_lds(int D, int block, int ncol_max, int mrows, int w, int R) {
     (void)R;
     const size_t nlut = static_cast<size_t>(lut_floats(D));
     const size_t macc = (static_cast<size_t>(mrows) * 9 * w + 3) & ~static_cast<size_t>(3);
-    const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * (kRawStride + 2 * kBwdStride);
+    const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * (kBwdRawStride + 2 * kBwdStride);
     const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
     return sizeof(float) * (2 * nlut + macc + std::max(stage, scratch));
 }
