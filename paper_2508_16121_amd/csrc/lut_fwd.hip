@@ -125,19 +125,23 @@ __device__ __forceinline__ void seg_columns(const Geo& g, int xs, int& clo, int&
 }
 
 // Per-wave staging of the forward (floats per map column): the raw rows (top at 0..8, row
-// difference at 12..20) and the blended row (nine values).  A wave's lanes read about 32
-// consecutive columns at once, so the strides are odd and the columns fall on distinct LDS
-// banks; 16-byte-aligned strides of 12 and 24 (4 and 8 columns per bank, vector accesses)
-// made the 4K apply about 2 % slower (56.4 against 55.0-55.2 us for odd pairs from 9 to 13
-// and 19 to 23).
-constexpr int kFMapStride = 13;
-constexpr int kFRawStride = 21;
+// difference at 12..20) and the blended row (nine values).  Usually a wave's lanes read about
+// 32 consecutive columns at once, so the strides are odd (13 / 21, scalar accesses) and the
+// columns fall on distinct LDS banks; 16-byte-aligned strides of 12 and 24 put 4 and 8 of
+// them on each bank and made the 4K apply about 2 % slower (56.4 against 55.0-55.2 us for odd
+// pairs from 9 to 13 and 19 to 23).  When a segment spans at most kVecStageCols columns (a
+// coarse map, e.g. one weight per image) those aligned strides are conflict-free as well and
+// their vector accesses take fewer LDS instructions, so VST selects them.
+constexpr int kVecStageCols = 8;
+template <bool VST> struct Stg { static constexpr int map = 13, raw = 21; };
+template <> struct Stg<true> { static constexpr int map = 12, raw = 24; };
 constexpr int kFRawDiff = 12;
+inline bool vec_stage(int ncol_max) { return ncol_max <= kVecStageCols; }
 
 // Stage the raw map rows around a tile row for the segment's columns: per column the nine
 // channels of row iv ("top") and their difference to row iv+1 ("diff").  Rewritten only when
 // the wave moves to another segment or another pair of map rows.
-template <typename MT>
+template <typename MT, bool VST>
 __device__ __forceinline__ void stage_raw(const ApplyLaunch& a, const Geo& g, int iv, int clo, int ncols,
                                           float* raw) {
     const int lane = threadIdx.x & (kWave - 1);
@@ -153,23 +157,49 @@ __device__ __forceinline__ void stage_raw(const ApplyLaunch& a, const Geo& g, in
             v0[l] = ldf<MT>(src + l * mplane);
             v1[l] = ldf<MT>(src + l * mplane + rowd);
         }
-        float* dst = raw + j * kFRawStride;
+        float* dst = raw + j * Stg<VST>::raw;
+        if (VST) {
+            *reinterpret_cast<float4*>(dst) = make_float4(v0[0], v0[1], v0[2], v0[3]);
+            *reinterpret_cast<float4*>(dst + 4) = make_float4(v0[4], v0[5], v0[6], v0[7]);
+            dst[8] = v0[8];
+            *reinterpret_cast<float4*>(dst + 12) =
+                make_float4(v1[0] - v0[0], v1[1] - v0[1], v1[2] - v0[2], v1[3] - v0[3]);
+            *reinterpret_cast<float4*>(dst + 16) =
+                make_float4(v1[4] - v0[4], v1[5] - v0[5], v1[6] - v0[6], v1[7] - v0[7]);
+            dst[20] = v1[8] - v0[8];
+        } else {
 #pragma unroll
-        for (int l = 0; l < 9; ++l) {
-            dst[l] = v0[l];
-            dst[kFRawDiff + l] = v1[l] - v0[l];
+            for (int l = 0; l < 9; ++l) {
+                dst[l] = v0[l];
+                dst[kFRawDiff + l] = v1[l] - v0[l];
+            }
         }
     }
 }
 
 // Blend the staged rows for one tile row: stage[col][l] = top + dv * diff.
+template <bool VST>
 __device__ __forceinline__ void blend_rows(const float* raw, float* stage, int ncols, float dv) {
     const int lane = threadIdx.x & (kWave - 1);
     for (int j = lane; j < ncols; j += kWave) {
-        const float* src = raw + j * kFRawStride;
-        float* dst = stage + j * kFMapStride;
+        const float* src = raw + j * Stg<VST>::raw;
+        float* dst = stage + j * Stg<VST>::map;
+        if (VST) {
+            const float4 t0 = *reinterpret_cast<const float4*>(src);
+            const float4 t1 = *reinterpret_cast<const float4*>(src + 4);
+            const float t2 = src[8];
+            const float4 d0 = *reinterpret_cast<const float4*>(src + 12);
+            const float4 d1 = *reinterpret_cast<const float4*>(src + 16);
+            const float d2 = src[20];
+            *reinterpret_cast<float4*>(dst) =
+                make_float4(fmaf(dv, d0.x, t0.x), fmaf(dv, d0.y, t0.y), fmaf(dv, d0.z, t0.z), fmaf(dv, d0.w, t0.w));
+            *reinterpret_cast<float4*>(dst + 4) =
+                make_float4(fmaf(dv, d1.x, t1.x), fmaf(dv, d1.y, t1.y), fmaf(dv, d1.z, t1.z), fmaf(dv, d1.w, t1.w));
+            dst[8] = fmaf(dv, d2, t2);
+        } else {
 #pragma unroll
-        for (int l = 0; l < 9; ++l) dst[l] = fmaf(dv, src[kFRawDiff + l], src[l]);
+            for (int l = 0; l < 9; ++l) dst[l] = fmaf(dv, src[kFRawDiff + l], src[l]);
+        }
     }
 }
 
@@ -183,7 +213,7 @@ struct GridTile {
     int Ds, Dsp;
 };
 
-template <typename IO, bool FASTMAP, bool VEC, bool GRID>
+template <typename IO, bool FASTMAP, bool VEC, bool GRID, bool VST>
 __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g, const float* Tl,
                                              const float* stage, int clo, int D, int y, int xs,
                                              const float (&px)[3][4], const float (&bias3)[3],
@@ -204,9 +234,9 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
     float out[3][4];
     float r0[9], d01[9], d12[9];
     if (FASTMAP) {
-        const float* s0 = stage + (c0 - clo) * kFMapStride;
-        const float* s1 = stage + (min(c0 + 1, g.w - 1) - clo) * kFMapStride;
-        const float* s2 = stage + (min(c0 + 2, g.w - 1) - clo) * kFMapStride;
+        const float* s0 = stage + (c0 - clo) * Stg<VST>::map;
+        const float* s1 = stage + (min(c0 + 1, g.w - 1) - clo) * Stg<VST>::map;
+        const float* s2 = stage + (min(c0 + 2, g.w - 1) - clo) * Stg<VST>::map;
 #pragma unroll
         for (int l = 0; l < 9; ++l) {
             const float a0 = s0[l], a1 = s1[l], a2 = s2[l];
@@ -227,8 +257,8 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
             int ck; uint32_t rk;
             axis_left(g.ax, min(x0 + k, g.W - 1), ck, rk);
             const float du = static_cast<float>(rk) * g.ax.inv;
-            const float* s0 = stage + (ck - clo) * kFMapStride;
-            const float* s1 = stage + (min(ck + 1, g.w - 1) - clo) * kFMapStride;
+            const float* s0 = stage + (ck - clo) * Stg<VST>::map;
+            const float* s1 = stage + (min(ck + 1, g.w - 1) - clo) * Stg<VST>::map;
 #pragma unroll
             for (int l = 0; l < 9; ++l) S[l] = fmaf(du, s1[l] - s0[l], s0[l]);
         }
@@ -329,7 +359,7 @@ constexpr int apply_threads() { return (sizeof(IO) == 2 && (GRID || !FASTMAP)) ?
 // run per wave, so a wave keeps its staged raw map rows for about h/H of a map cell's
 // height in pixel rows and only re-reads the map when the segment or the pair of map rows
 // changes.  VEC is uniform per image, so the hot loop has a single load/store form.
-template <typename IO, typename MT, bool FASTMAP, bool VEC, bool GRID>
+template <typename IO, typename MT, bool FASTMAP, bool VEC, bool GRID, bool VST>
 __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, int b, int ta, int tb,
                                           int wave, int nw, float* Tl, float* Gl, float* aux, float* stage,
                                           float* raw) {
@@ -406,19 +436,19 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
         axis_left(g.ay, y, iv, remv);
         if (seg != st_seg || iv != st_iv) {
             seg_columns(g, xs, clo, ncols);
-            stage_raw<MT>(a, g, iv, clo, ncols, raw);
+            stage_raw<MT, VST>(a, g, iv, clo, ncols, raw);
             st_seg = seg;
             st_iv = iv;
             wave_sync();
         }
-        blend_rows(raw, stage, ncols, static_cast<float>(remv) * g.ay.inv);
+        blend_rows<VST>(raw, stage, ncols, static_cast<float>(remv) * g.ay.inv);
         wave_sync();
         if (GRID) {
             uint32_t ry;
             axis_left(gay, y, gt.iy, ry);
             gt.dy = static_cast<float>(ry) * gay.inv;
         }
-        compute_tile<IO, FASTMAP, VEC, GRID>(a, g, Tl, stage, clo, D, y, xs, px, bias3, gt);
+        compute_tile<IO, FASTMAP, VEC, GRID, VST>(a, g, Tl, stage, clo, D, y, xs, px, bias3, gt);
         wave_sync();   // the stage region is rewritten for the next tile
         advance(seg, yr, k);
         if (EARLY && k < k1) load_tile<IO, VEC>(a, g, ya + yr, seg * kSeg, px);
@@ -430,7 +460,7 @@ int apply_max_block(svdlut_dtype io, bool fast_map, bool grid) {
 }
 
 // Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave runs.
-template <typename IO, typename MT, bool FASTMAP, bool GRID>
+template <typename IO, typename MT, bool FASTMAP, bool GRID, bool VST>
 __global__ void __launch_bounds__((apply_threads<IO, FASTMAP, GRID>())) apply_kernel(ApplyLaunch a) {
     extern __shared__ float smem[];
     const int D = a.D;
@@ -441,8 +471,8 @@ __global__ void __launch_bounds__((apply_threads<IO, FASTMAP, GRID>())) apply_ke
     // wave index as a scalar: everything derived from it (tile runs, rows, segments) stays
     // wave-uniform, so the tile bookkeeping runs on the scalar unit with uniform branches
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    float* stage = aux + wave * a.ncol_max * (kFMapStride + kFRawStride);
-    float* raw = stage + a.ncol_max * kFMapStride;
+    float* stage = aux + wave * a.ncol_max * (Stg<VST>::map + Stg<VST>::raw);
+    float* raw = stage + a.ncol_max * Stg<VST>::map;
 
     const int G = gridDim.x;
     const int lb = logical_block(blockIdx.x, G);
@@ -457,9 +487,9 @@ __global__ void __launch_bounds__((apply_threads<IO, FASTMAP, GRID>())) apply_ke
         const int ta = static_cast<int>(t0 - g.tile0);
         const int tb = static_cast<int>(te - g.tile0);
         if (g.vec_ok)
-            run_image<IO, MT, FASTMAP, true, GRID>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
+            run_image<IO, MT, FASTMAP, true, GRID, VST>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
         else
-            run_image<IO, MT, FASTMAP, false, GRID>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
+            run_image<IO, MT, FASTMAP, false, GRID, VST>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
         t0 = te;
         __syncthreads();   // every wave is done with Tl and aux before the next image
     }
@@ -482,22 +512,27 @@ size_t apply_lds_bytes(int D, int R, int block, int ncol_max, int Ds) {
     (void)R;
     const size_t grid = Ds > 0 ? static_cast<size_t>((grid_floats(Ds) + 3) & ~3) : 0;
     const size_t scratch = static_cast<size_t>(2) * 9 * D * 8;
-    const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * (kFMapStride + kFRawStride);
+    const int per_col = vec_stage(ncol_max) ? Stg<true>::map + Stg<true>::raw : Stg<false>::map + Stg<false>::raw;
+    const size_t stage = static_cast<size_t>(block / kWave) * ncol_max * per_col;
     return sizeof(float) * (lut + grid + std::max(scratch, stage));
+}
+
+template <typename IO, typename MT, bool FASTMAP, bool GRID>
+static void launch_staged(const ApplyLaunch& a, size_t lds, hipStream_t st) {
+    if (vec_stage(a.ncol_max))
+        hipLaunchKernelGGL((apply_kernel<IO, MT, FASTMAP, GRID, true>), dim3(a.grid), dim3(a.block), lds, st, a);
+    else
+        hipLaunchKernelGGL((apply_kernel<IO, MT, FASTMAP, GRID, false>), dim3(a.grid), dim3(a.block), lds, st, a);
 }
 
 template <typename IO, typename MT>
 static void launch_typed(const ApplyLaunch& a, size_t lds, hipStream_t st) {
     if (a.K > 0) {
-        if (a.fast_map)
-            hipLaunchKernelGGL((apply_kernel<IO, MT, true, true>), dim3(a.grid), dim3(a.block), lds, st, a);
-        else
-            hipLaunchKernelGGL((apply_kernel<IO, MT, false, true>), dim3(a.grid), dim3(a.block), lds, st, a);
+        if (a.fast_map) launch_staged<IO, MT, true, true>(a, lds, st);
+        else launch_staged<IO, MT, false, true>(a, lds, st);
     } else {
-        if (a.fast_map)
-            hipLaunchKernelGGL((apply_kernel<IO, MT, true, false>), dim3(a.grid), dim3(a.block), lds, st, a);
-        else
-            hipLaunchKernelGGL((apply_kernel<IO, MT, false, false>), dim3(a.grid), dim3(a.block), lds, st, a);
+        if (a.fast_map) launch_staged<IO, MT, true, false>(a, lds, st);
+        else launch_staged<IO, MT, false, false>(a, lds, st);
     }
 }
 
