@@ -89,7 +89,7 @@ def load(path: str = LIB_PATH):
     if _lib is not None:
         return _lib
     if not os.path.exists(path):
-        raise ImportError(f"{path} is missing: build it with `python -m paper_2508_16121_amd.build`")
+        raise ImportError(f"{path} is missing: build it with `python paper_2508_16121_amd/build.py`")
     lib = C.CDLL(path)
     for name, (res, args) in SIGS.items():
         fn = getattr(lib, name, None)

@@ -1,6 +1,6 @@
 """Build libsvdlut.so (all HIP sources of csrc/) for gfx950 with hipcc, in-tree.
 
-    python -m paper_2508_16121_amd.build        # or build() from Python
+    python paper_2508_16121_amd/build.py        # or build() of __graft_entry__.py
 
 Each source compiles to an object under _build/ in parallel, then one shared library is
 linked next to this file.  Every call recompiles.
