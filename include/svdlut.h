@@ -159,6 +159,29 @@ svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io,
                                hipStream_t stream);
 
 /*
+ * svdlut_apply_bwd_noalloc — svdlut_apply_bwd for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same arguments, kernels, outputs and determinism, minus ws and ws_bytes.  The dT partials
+ * go to a buffer of SVDLUT_NOALLOC_SCRATCH_BYTES that the library holds in device memory
+ * on every GPU it runs on until the process ends; the call itself allocates nothing.  Its
+ * contents are ignored on entry (every partial is overwritten), so nothing needs clearing.
+ * Every call on one GPU shares that GPU's buffer: calls that overlap in time on one GPU
+ * (two streams, two host threads) race and must be serialised by the caller.
+ * Errors: those of svdlut_apply_bwd, plus EINVAL when the factor gradients are requested
+ * and svdlut_apply_bwd_workspace_size(B, D) exceeds SVDLUT_NOALLOC_SCRATCH_BYTES (e.g. at
+ * D = 40 up to B = 369 fits, at D = 33 up to B = 577), and EDEVICE if the buffer's address
+ * cannot be obtained.
+ */
+#define SVDLUT_NOALLOC_SCRATCH_BYTES (24u * 1024u * 1024u)
+svdlut_status svdlut_apply_bwd_noalloc(const void* x, const void* dy, svdlut_dtype io,
+                                       const float* U, const float* s, const float* V,
+                                       const void* map, svdlut_dtype map_dt,
+                                       void* dx, float* dU, float* ds, float* dV,
+                                       float* dmap, float* dbias,
+                                       int32_t B, int32_t H, int32_t W, int32_t h, int32_t w,
+                                       int32_t D, int32_t R, hipStream_t stream);
+
+/*
  * svdlut_apply_grid_bwd — gradients of a scalar loss through svdlut_apply_grid, given
  * dy = dL/dY.  The LUT and map part is svdlut_apply_bwd (same outputs, same rules); the
  * grid part adds, by the chain rule of the slicing (supp. Sec. "2D Slicing"), per grid k of

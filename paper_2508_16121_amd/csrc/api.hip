@@ -94,6 +94,72 @@ static int blocks_per_cu(int D, int R, int block, int ncol_max, const DeviceInfo
     return std::max(1, std::min(by_lds, by_waves));
 }
 
+// Argument checks of svdlut_apply_bwd and svdlut_apply_bwd_noalloc (no HIP call).
+static svdlut_status check_apply_bwd(const void* x, const void* dy, svdlut_dtype io, const float* U, const float* s,
+                                     const float* V, const void* map, svdlut_dtype map_dt, const float* dU,
+                                     const float* ds, const float* dV, int32_t B, int32_t H, int32_t W, int32_t h,
+                                     int32_t w, int32_t D, int32_t R) {
+    if (!x || !dy || !U || !s || !V || !map) return fail(SVDLUT_EINVAL, "apply_bwd: null input pointer");
+    const int nfac = (dU != nullptr) + (ds != nullptr) + (dV != nullptr);
+    if (nfac != 0 && nfac != 3) return fail(SVDLUT_EINVAL, "apply_bwd: dU, ds, dV must be all set or all NULL");
+    SVDLUT_TRY(check_dtype(io, "apply_bwd io"));
+    SVDLUT_TRY(check_dtype(map_dt, "apply_bwd map"));
+    if (B < 1) return fail(SVDLUT_EINVAL, "apply_bwd: B must be >= 1");
+    if (!dims_ok(H) || !dims_ok(W) || !dims_ok(h) || !dims_ok(w))
+        return fail(SVDLUT_EINVAL, "apply_bwd: H, W, h, w must be in [1, 65535]");
+    return check_lut_dims(D, R);
+}
+
+// The backward launch once the arguments (and the partial buffer ws) are settled.
+static svdlut_status apply_bwd_launch(const void* x, const void* dy, svdlut_dtype io, const float* U, const float* s,
+                                      const float* V, const void* map, svdlut_dtype map_dt, void* dx, float* dU,
+                                      float* ds, float* dV, float* dmap, float* dbias, int32_t B, int32_t H,
+                                      int32_t W, int32_t h, int32_t w, int32_t D, int32_t R, void* ws,
+                                      hipStream_t stream) {
+    if (!dx && !dU && !dmap && !dbias) return SVDLUT_OK;
+    BwdLaunch a{};
+    a.x = x; a.dy = dy; a.U = U; a.s = s; a.V = V; a.map = map;
+    a.dx = dx; a.dU = dU; a.ds = ds; a.dV = dV; a.dmap = dmap; a.dbias = dbias;
+    a.dT = static_cast<float*>(ws);
+    a.B = B; a.H = H; a.W = W; a.h = h; a.w = w; a.D = D; a.R = R;
+    a.io = io; a.map_dt = map_dt;
+    return launch_apply_bwd(a, stream);
+}
+
+// ---------------------------------------------------------------- allocation-free backward
+// svdlut_apply_bwd_noalloc keeps the backward's dT partials in this library-owned array
+// instead of a caller workspace.  Host code never passes the array's name as an address:
+// each device's copy is looked up once with hipGetSymbolAddress, with that device current,
+// and that pointer is what the kernels receive.
+constexpr int kScratchDevices = 64;
+static __device__ __align__(256) unsigned char scratch[SVDLUT_NOALLOC_SCRATCH_BYTES];
+
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kScratchDevices] = {};
+
+static svdlut_status scratch_for_current_device(void** out) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(SVDLUT_EDEVICE, "apply_bwd_noalloc: hipGetDevice failed");
+    }
+    if (dev < 0 || dev >= kScratchDevices)
+        return fail(SVDLUT_EUNSUPPORTED, "apply_bwd_noalloc: device index beyond the library's table");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return fail(SVDLUT_EDEVICE, std::string("apply_bwd_noalloc: hipGetSymbolAddress failed: ") +
+                                            hipGetErrorString(e));
+        }
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return SVDLUT_OK;
+}
+
 }  // namespace svdlut
 
 using namespace svdlut;
@@ -262,28 +328,36 @@ svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io, c
                                void* dx, float* dU, float* ds, float* dV, float* dmap, float* dbias,
                                int32_t B, int32_t H, int32_t W, int32_t h, int32_t w, int32_t D,
                                int32_t R, void* ws, size_t ws_bytes, hipStream_t stream) {
-    if (!x || !dy || !U || !s || !V || !map) return fail(SVDLUT_EINVAL, "apply_bwd: null input pointer");
-    const int nfac = (dU != nullptr) + (ds != nullptr) + (dV != nullptr);
-    if (nfac != 0 && nfac != 3) return fail(SVDLUT_EINVAL, "apply_bwd: dU, ds, dV must be all set or all NULL");
-    SVDLUT_TRY(check_dtype(io, "apply_bwd io"));
-    SVDLUT_TRY(check_dtype(map_dt, "apply_bwd map"));
-    if (B < 1) return fail(SVDLUT_EINVAL, "apply_bwd: B must be >= 1");
-    if (!dims_ok(H) || !dims_ok(W) || !dims_ok(h) || !dims_ok(w))
-        return fail(SVDLUT_EINVAL, "apply_bwd: H, W, h, w must be in [1, 65535]");
-    SVDLUT_TRY(check_lut_dims(D, R));
-    if (nfac == 3) {
+    SVDLUT_TRY(check_apply_bwd(x, dy, io, U, s, V, map, map_dt, dU, ds, dV, B, H, W, h, w, D, R));
+    const bool factors = dU != nullptr;
+    if (factors) {
         if (!ws) return fail(SVDLUT_EINVAL, "apply_bwd: workspace required for dU, ds, dV");
         if (ws_bytes < bwd_workspace_bytes(B, D))
             return fail(SVDLUT_EINVAL, "apply_bwd: workspace smaller than svdlut_apply_bwd_workspace_size()");
     }
-    if (!dx && nfac == 0 && !dmap && !dbias) return SVDLUT_OK;
-    BwdLaunch a{};
-    a.x = x; a.dy = dy; a.U = U; a.s = s; a.V = V; a.map = map;
-    a.dx = dx; a.dU = dU; a.ds = ds; a.dV = dV; a.dmap = dmap; a.dbias = dbias;
-    a.dT = static_cast<float*>(ws);
-    a.B = B; a.H = H; a.W = W; a.h = h; a.w = w; a.D = D; a.R = R;
-    a.io = io; a.map_dt = map_dt;
-    return launch_apply_bwd(a, stream);
+    return apply_bwd_launch(x, dy, io, U, s, V, map, map_dt, dx, dU, ds, dV, dmap, dbias, B, H, W, h, w, D, R,
+                            ws, stream);
+}
+
+svdlut_status svdlut_apply_bwd_noalloc(const void* x, const void* dy, svdlut_dtype io, const float* U,
+                                       const float* s, const float* V, const void* map, svdlut_dtype map_dt,
+                                       void* dx, float* dU, float* ds, float* dV, float* dmap, float* dbias,
+                                       int32_t B, int32_t H, int32_t W, int32_t h, int32_t w, int32_t D,
+                                       int32_t R, hipStream_t stream) {
+    SVDLUT_TRY(check_apply_bwd(x, dy, io, U, s, V, map, map_dt, dU, ds, dV, B, H, W, h, w, D, R));
+    const bool factors = dU != nullptr;
+    void* ws = nullptr;
+    if (factors) {
+        const size_t need = bwd_workspace_bytes(B, D);
+        if (need > static_cast<size_t>(SVDLUT_NOALLOC_SCRATCH_BYTES))
+            return fail(SVDLUT_EINVAL, "apply_bwd_noalloc: B = " + std::to_string(B) + ", D = " + std::to_string(D) +
+                                           " needs " + std::to_string(need) +
+                                           " bytes of scratch, more than the library's " +
+                                           std::to_string(static_cast<size_t>(SVDLUT_NOALLOC_SCRATCH_BYTES)));
+        SVDLUT_TRY(scratch_for_current_device(&ws));
+    }
+    return apply_bwd_launch(x, dy, io, U, s, V, map, map_dt, dx, dU, ds, dV, dmap, dbias, B, H, W, h, w, D, R,
+                            ws, stream);
 }
 
 }  // extern "C"

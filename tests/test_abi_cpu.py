@@ -205,3 +205,20 @@ def test_paper_generator_layout_matches_oracle(lib):
         assert a == b
         assert sum(int(np.prod(s)) for s in a) == lib.svdlut_paper_generator_param_count(33, 8, K, 17)
         assert pm.init_params(33, 8, K, 17).size == lib.svdlut_paper_generator_param_count(33, 8, K, 17)
+
+
+def test_noalloc_backward_validates_before_any_hip_call(lib):
+    """The allocation-free backward rejects bad arguments, and a batch whose partials exceed
+    the library's buffer, with a status and a message before any HIP call."""
+    fake = C.c_void_p(0x1000)
+    head = [fake, fake, 0, fake, fake, fake, fake, 0, None]
+    # partial factor-gradient trio
+    assert lib.svdlut_apply_bwd_noalloc(*head, fake, None, fake, None, None, 4, 4, 4, 1, 1, 33, 8, None) == 1
+    assert "all set" in _err(lib)
+    # B too large for the buffer (only when the factor gradients are requested)
+    assert lib.svdlut_apply_bwd_noalloc(*head, fake, fake, fake, None, None, 600, 4, 4, 1, 1, 33, 8, None) == 1
+    assert "scratch" in _err(lib)
+    assert lib.svdlut_apply_bwd_noalloc(*head, fake, fake, fake, None, None, 400, 4, 4, 1, 1, 40, 8, None) == 1
+    # the usual range checks
+    assert lib.svdlut_apply_bwd_noalloc(*head, fake, fake, fake, None, None, 1, 4, 4, 1, 1, 41, 8, None) == 1
+    assert lib.svdlut_apply_bwd_noalloc(*head, fake, fake, fake, None, None, 0, 4, 4, 1, 1, 33, 8, None) == 1
