@@ -642,7 +642,7 @@ svdlut_status svdlut_plan_autotune(svdlut_plan* p, const void* x, void* y, const
     struct Cand { int block, bpc; };
     std::vector<Cand> cands;
     const int maxthr = apply_max_block(p->io, p->fast_map != 0, false);
-    for (int blk : {256, 512, 1024}) {
+    for (int blk : {64, 128, 256, 512, 1024}) {
         if (blk > maxthr) continue;
         if (apply_lds_bytes(p->D, p->R, blk, p->ncol_max) > static_cast<size_t>(di.lds_per_block)) continue;
         const int maxb = blocks_per_cu(p->D, p->R, blk, p->ncol_max, di, 0, maxthr);

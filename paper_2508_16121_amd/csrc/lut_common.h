@@ -15,31 +15,37 @@ template <typename T> __device__ __forceinline__ void stf(T* p, float v);
 template <> __device__ __forceinline__ void stf<float>(float* p, float v) { *p = v; }
 template <> __device__ __forceinline__ void stf<__half>(__half* p, float v) { *p = __float2half_rn(v); }
 
-// Four consecutive elements; p must be aligned to 4 elements.
+// Four consecutive elements; p must be aligned to 4 elements.  Image planes are streamed:
+// read once and written once per launch, so their vector accesses carry the nontemporal
+// hint, which keeps them from displacing the LUT factors and the spatial map (read by every
+// workgroup) in the caches (4K apply 55 -> 52.5 us).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
 template <typename T> __device__ __forceinline__ void ld4(const T* p, float (&o)[4]);
 template <> __device__ __forceinline__ void ld4<float>(const float* p, float (&o)[4]) {
-    const float4 v = *reinterpret_cast<const float4*>(p);
+    const f32x4 v = __builtin_nontemporal_load(reinterpret_cast<const f32x4*>(p));
     o[0] = v.x; o[1] = v.y; o[2] = v.z; o[3] = v.w;
 }
 template <> __device__ __forceinline__ void ld4<__half>(const __half* p, float (&o)[4]) {
-    const uint2 v = *reinterpret_cast<const uint2*>(p);
-    const __half2 a = *reinterpret_cast<const __half2*>(&v.x);
-    const __half2 b = *reinterpret_cast<const __half2*>(&v.y);
+    const u32x2 v = __builtin_nontemporal_load(reinterpret_cast<const u32x2*>(p));
+    const uint32_t vx = v.x, vy = v.y;
+    const __half2 a = *reinterpret_cast<const __half2*>(&vx);
+    const __half2 b = *reinterpret_cast<const __half2*>(&vy);
     const float2 fa = __half22float2(a), fb = __half22float2(b);
     o[0] = fa.x; o[1] = fa.y; o[2] = fb.x; o[3] = fb.y;
 }
 
 template <typename T> __device__ __forceinline__ void st4(T* p, const float (&o)[4]);
 template <> __device__ __forceinline__ void st4<float>(float* p, const float (&o)[4]) {
-    *reinterpret_cast<float4*>(p) = make_float4(o[0], o[1], o[2], o[3]);
+    const f32x4 v = {o[0], o[1], o[2], o[3]};
+    __builtin_nontemporal_store(v, reinterpret_cast<f32x4*>(p));
 }
 template <> __device__ __forceinline__ void st4<__half>(__half* p, const float (&o)[4]) {
     __half2 a = __floats2half2_rn(o[0], o[1]);
     __half2 b = __floats2half2_rn(o[2], o[3]);
-    uint2 v;
-    v.x = *reinterpret_cast<uint32_t*>(&a);
-    v.y = *reinterpret_cast<uint32_t*>(&b);
-    *reinterpret_cast<uint2*>(p) = v;
+    const u32x2 v = {*reinterpret_cast<uint32_t*>(&a), *reinterpret_cast<uint32_t*>(&b)};
+    __builtin_nontemporal_store(v, reinterpret_cast<u32x2*>(p));
 }
 
 // The lane's 4 pixels [x0, x0+4) of one row, x0 < n.  VEC: one aligned vector access
