@@ -5,8 +5,15 @@
 Headline (`value`): svdlut_apply on one 3840x2160 float32 frame (33x33 LUTs at rank 8,
 reconstruction fused, 480x270 spatial map), in Mpix/s, inputs resident in HBM.  Each timed
 step is one launch; four disjoint buffer sets rotate so that the 256 MB Infinity Cache
-cannot serve a step from the previous one.  The other hot-path rows are timed in the same
-run and reported under "rows".  Prints ONE JSON line.
+cannot serve a step from the previous one.  `roofline.achieved` is the algorithmic bytes of
+one launch over the back-to-back step time.  The other hot-path rows are timed in the same
+run, before the headline, and reported under "rows".  Prints ONE JSON line.
+
+    python bench.py --summarize-trace DIR --steps K --warmup W --command "..."
+    python bench.py --summarize-traffic FETCH_DIR WRITE_DIR --command "cmd1 ;; cmd2"
+
+turn rocprofv3 CSV output of `bench.py --rows none` runs into the summaries under profiles/
+that the bench line cites (no GPU needed).
 """
 from __future__ import annotations
 
@@ -38,6 +45,13 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run device-to-device copies of one 4K fp32 frame (99.5 MB), the reference "
                          "kernel that calibrates HBM byte counters in a profiler run")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="no GPU: summarise a rocprofv3 --kernel-trace CSV run of `bench.py --rows none` "
+                         "(same --steps/--warmup) into profiles/apply_4k_fp32_kernel_trace.json")
+    ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="no GPU: summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "`bench.py --rows none --copy-probe` into profiles/apply_4k_fp32_traffic.json")
+    ap.add_argument("--command", default="", help="the profiler command recorded in a summary")
     return ap.parse_args()
 
 
@@ -70,25 +84,119 @@ def kernel_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per launch of the 4K apply from the committed counter summary, or None when
-    the kernel sources changed since the counters were taken."""
+TRACE_FILE = os.path.join(ROOT, "profiles", "apply_4k_fp32_kernel_trace.json")
+HEADLINE_KERNEL = "apply_kernel<float, float, true, false, false>"
+
+
+def _current_summary(path):
+    """A committed profile summary, or None when the kernel sources changed since it was taken."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(path) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
-    if t.get("kernel_hash") != kernel_hash():
+    return t if t.get("kernel_hash") == kernel_hash() else None
+
+
+def measured_traffic():
+    """HBM bytes per launch of the 4K apply from the committed counter summary (or None)."""
+    t = _current_summary(TRAFFIC_FILE)
+    return t.get("bytes_per_launch") if t else None
+
+
+def profiled_launch():
+    """Mean duration of the timed 4K launches under rocprofv3 from the committed trace summary
+    (or None)."""
+    t = _current_summary(TRACE_FILE)
+    if not t:
         return None
-    return t.get("bytes_per_launch")
+    return {"avg_ms": round(t["timed_avg_ns"] * 1e-6, 5), "source": os.path.relpath(TRACE_FILE, ROOT)}
+
+
+def _csvs(d, suffix):
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(d, "**", "*" + suffix), recursive=True)):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def _kernel_rows(rows, name):
+    """Dispatches of the headline kernel variant, in start order (one row per dispatch)."""
+    sel = {}
+    for r in rows:
+        if name in r["Kernel_Name"]:
+            sel.setdefault(int(r.get("Dispatch_Id", r.get("Correlation_Id", 0))), r)
+    return [sel[k] for k in sorted(sel, key=lambda k: int(sel[k]["Start_Timestamp"]))]
+
+
+def summarize_trace(args):
+    rows = _kernel_rows(_csvs(args.summarize_trace, "kernel_trace.csv"), HEADLINE_KERNEL)
+    dur = np.array([int(r["End_Timestamp"]) - int(r["Start_Timestamp"]) for r in rows], dtype=np.float64)
+    # launch order of `bench.py --rows none`: warm-up, the back-to-back timed run, then the
+    # event-pair run of the same number of launches
+    w, k = args.warmup, args.steps
+    if len(dur) < w + 2 * k:
+        raise SystemExit(f"expected {w + 2 * k} dispatches of {HEADLINE_KERNEL}, found {len(dur)}")
+    timed = dur[w:w + k]
+    out = {"kernel": HEADLINE_KERNEL + " (svdlut_apply, 1x3x2160x3840 fp32, D=33 R=8, map 9x270x480 fp32)",
+           "kernel_hash": kernel_hash(), "kernel_hash_sources": list(KERNEL_SOURCES),
+           "dispatches": int(len(dur)), "warmup": w, "steps": k,
+           "timed_avg_ns": round(float(timed.mean()), 1), "timed_median_ns": float(np.median(timed)),
+           "timed_min_ns": float(timed.min()), "timed_max_ns": float(timed.max()),
+           "all_avg_ns": round(float(dur.mean()), 1), "command": args.command}
+    with open(TRACE_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
+def summarize_traffic(args):
+    def per_dispatch(d, counter):
+        rows = _csvs(d, "counter_collection.csv")
+        acc = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            key = (r["Kernel_Name"], int(r["Dispatch_Id"]))
+            acc[key] = acc.get(key, 0.0) + float(r["Counter_Value"])
+        heads = {i: x for (n, i), x in acc.items() if HEADLINE_KERNEL in n}
+        # the probe's device-to-device copies run after the last headline launch (the copies
+        # before it upload the inputs from the host)
+        last = max(heads)
+        probe = [x for (n, i), x in acc.items() if "copyBuffer" in n and i > last]
+        return float(np.mean(list(heads.values()))), float(np.mean(probe))
+    fa, fc = per_dispatch(args.summarize_traffic[0], "FETCH_SIZE")
+    wa, wc = per_dispatch(args.summarize_traffic[1], "WRITE_SIZE")
+    frame = 2160 * 3840 * 3 * 4
+    fs, ws = frame / 1024.0 / fc, frame / 1024.0 / wc
+    rd, wr = int(fa * 1024 * fs), int(wa * 1024 * ws)
+    out = {"kernel": HEADLINE_KERNEL + " (svdlut_apply, 1x3x2160x3840 fp32, D=33 R=8, map 9x270x480 fp32)",
+           "kernel_hash": kernel_hash(), "kernel_hash_sources": list(KERNEL_SOURCES),
+           "fetch_size_kib_per_dispatch": round(fa, 2), "write_size_kib_per_dispatch": round(wa, 2),
+           "copy_probe": {"bytes_read": frame, "bytes_written": frame, "fetch_size_kib": round(fc, 2),
+                          "write_size_kib": round(wc, 2)},
+           "fetch_scale": round(fs, 5), "write_scale": round(ws, 5),
+           "bytes_read_per_launch": rd, "bytes_written_per_launch": wr, "bytes_per_launch": rd + wr,
+           "algorithmic_bytes_per_launch": HEADLINE_BYTES, "commands": args.command.split(" ;; ")}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
+HEADLINE_BYTES = 2160 * 3840 * 24 + 9 * 270 * 480 * 4 + 9 * 33 * 8 * 2 * 4 + 9 * 8 * 4
 
 
 def launch_times(fn, steps, warmup, torch):
-    """(ms per step, ms per launch) over `steps` calls of a one-kernel fn(i), both with HIP
+    """(ms per step, ms per event pair) over `steps` calls of a one-kernel fn(i), both with HIP
     events on the current stream (the stream the library launches on).  The first figure
-    brackets the whole run of `steps` back-to-back calls; the second comes from a separate run
-    in which every launch has its own event pair, i.e. the kernel's own duration without the
-    gaps between launches (the event packets themselves stay out of the first figure)."""
+    brackets the whole run of `steps` back-to-back calls and is the one every rate is computed
+    from.  The second comes from a separate run in which every launch has its own event pair;
+    the event packets add their own time (about 2 us per launch on this part), so it is an
+    upper bound of the launch duration, reported only for reference."""
     for i in range(warmup):
         fn(i)
     torch.cuda.synchronize()
@@ -130,10 +238,27 @@ def _oracle_band(rows_):
     return (y1 - y0) * W
 
 
-def cpu_baseline(case, budget_s):
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown CPU"
+
+
+# worker processes of the CPU baseline: every core of the affinity mask, but no more than the
+# 16 cores a one-GPU machine grants a job (more processes would only time-slice the same cores)
+CPU_SHARE = 16
+
+
+def cpu_baseline(case, budget_s, c1):
     """The fp64 oracle on the same 4K frame, timed on the host: one process on row bands until
-    about budget_s of work, and row bands over all usable cores (at most 16) with a process
-    pool, median of three runs.  Runs before the GPU is touched (the pool forks)."""
+    about budget_s of work, and the same rows as bands over a process pool on every usable
+    core, median of three runs; plus the oracle on the whole 256x256 frame of the plain config
+    (median of three single-process runs).  Runs before the GPU is touched (the pool forks)."""
     import multiprocessing as mp
     from oracle import lut as ol
     x, U, s, V, m = case.x[0], case.U[0], case.s[0], case.V[0], case.smap[0]
@@ -149,7 +274,8 @@ def cpu_baseline(case, budget_s):
         rows += min(band, H - y0)
         y0 += band
     single = px / t_total / 1e6
-    cores = max(1, min(16, len(os.sched_getaffinity(0))))
+    avail = len(os.sched_getaffinity(0))
+    cores = max(1, min(CPU_SHARE, avail))
     # all cores: the rows the single-process run covered, split into bands over a fork pool
     jobs = [(r, min(r + band, rows)) for r in range(0, rows, band)]
     runs = []
@@ -159,19 +285,21 @@ def cpu_baseline(case, budget_s):
             npx = sum(pool.map(_oracle_band, jobs, chunksize=1))
             runs.append(npx / (time.perf_counter() - t) / 1e6)
     multi = float(np.median(runs))
-    model = "unknown CPU"
-    try:
-        with open("/proc/cpuinfo") as f:
-            for line in f:
-                if line.startswith("model name"):
-                    model = line.split(":", 1)[1].strip()
-                    break
-    except OSError:
-        pass
+    # C1: the plain 256x256 frame, whole frame, one process (the full oracle: reconstruct + apply)
+    c1_runs = []
+    for _ in range(3):
+        t = time.perf_counter()
+        ol.apply(c1.x, c1.U, c1.s, c1.V, c1.smap)
+        c1_runs.append(time.perf_counter() - t)
+    c1_ms = float(np.median(c1_runs)) * 1e3
+    model = _cpu_model()
     return {"value": round(multi, 3), "unit": "Mpix/s", "cores": cores, "kind": "oracle",
             "single_core_value": round(single, 3),
             "sample": f"{rows} of {H} rows of the {W}x{H} frame (fp64 NumPy oracle): one process "
-                      f"{t_total:.1f} s; {cores} processes on 64-row bands, median of 3; {model}"}
+                      f"{t_total:.1f} s; {cores} processes on 64-row bands ({avail} cores in the affinity "
+                      f"mask), median of 3; {model}",
+            "c1": {"workload": "oracle apply (reconstruct + transform), whole 256x256 frame, D=17 R=4, map 9x32x32",
+                   "ms": round(c1_ms, 2), "mpix_s": round(256 * 256 / (c1_ms * 1e-3) / 1e6, 3), "cores": 1}}
 
 
 def row_g1(svd, torch, synth, args):
@@ -191,8 +319,8 @@ def row_g1(svd, torch, synth, args):
     npx = 2160 * 3840
     bytes_alg = npx * 24 + 9 * 270 * 480 * 4 + 9 * 33 * 8 * 2 * 4 + 9 * 8 * 4 + gr.nbytes + gw.nbytes + gb.nbytes
     return {"workload": "svdlut_apply_grid 1x3x2160x3840 fp32, D=33 R=8, map 9x270x480, K=6 grids x 3 planes 17x17",
-            "ms": round(ms, 5), "kernel_ms": round(ms_kernel, 5), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1),
-            "roofline": roof(bytes_alg, ms_kernel)}
+            "ms": round(ms, 5), "event_pair_ms": round(ms_kernel, 5), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1),
+            "roofline": roof(bytes_alg, ms)}
 
 
 def row_u1(svd, torch, synth, args):
@@ -490,14 +618,28 @@ def row_p1(svd, torch, synth, args):
 
 def main():
     args = parse()
+    if args.summarize_trace:
+        return summarize_trace(args)
+    if args.summarize_traffic:
+        return summarize_traffic(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
     import synth
     c2 = synth.frame_4k()                         # host inputs first, before the GPU is touched
-    cpu = cpu_baseline(c2, args.cpu_seconds) if args.cpu_seconds > 0 else None   # forks: before torch
+    cpu = (cpu_baseline(c2, args.cpu_seconds, synth.plain_256()) if args.cpu_seconds > 0
+           else None)                             # forks: before torch
     import torch
     import paper_2508_16121_amd as svd
+
+    # The other rows run first: the headline's warm-up launches then find the GPU's clocks in
+    # the state of sustained work rather than ramping up from idle.
+    want = {"c1", "c3", "c4", "c5", "g1", "g4", "sweep", "dims", "u1", "p1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
+    rows = {}
+    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep), ("dims", row_dims), ("u1", row_u1), ("p1", row_p1)):
+        if name in want:
+            rows[name] = fn(svd, torch, synth, args)
+            print(f"row {name} done", file=sys.stderr, flush=True)
 
     B, H, W, D, R, h, w = c2.shape
     npx = H * W
@@ -512,8 +654,9 @@ def main():
         b = sets[i % N_ROT]
         svd.apply(b["x"], b["U"], b["s"], b["V"], b["m"], out=b["y"])
 
-    ms, ms_kernel = launch_times(step, args.steps, args.warmup, torch)
+    ms, ms_pair = launch_times(step, args.steps, args.warmup, torch)
     bytes_alg = npx * (12 + 12) + 9 * h * w * 4 + 9 * D * R * 2 * 4 + 9 * R * 4
+    assert bytes_alg == HEADLINE_BYTES
     out = {
         "metric": "Mpix/s of 2D-LUT apply at 4K (fwd, fwd+bwd, batched); % of HBM peak",
         "value": round(npx / (ms * 1e-3) / 1e6, 1), "unit": "Mpix/s", "n_gpus": 1, "steps": args.steps,
@@ -521,8 +664,10 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": "svdlut_apply 1x3x2160x3840 fp32, D=33 R=8, map 9x270x480 fp32, fused reconstruction",
                    "global_batch": 1, "pixels": npx},
-        "roofline": dict(roof(bytes_alg, ms_kernel), traffic=measured_traffic(), kernel="apply_kernel",
-                         kernel_ms=round(ms_kernel, 5)),
+        # every step is one launch of the kernel on the library's stream, so the back-to-back
+        # step time is the launch duration the roofline is computed from
+        "roofline": dict(roof(bytes_alg, ms), traffic=measured_traffic(), kernel=HEADLINE_KERNEL,
+                         bytes_per_launch=bytes_alg, event_pair_ms=round(ms_pair, 5), rocprof=profiled_launch()),
     }
     if args.copy_probe:
         src = sets[0]["x"]
@@ -530,12 +675,6 @@ def main():
         ms_copy = event_time(lambda i: dst.copy_(src), max(5, args.steps // 4), 2, torch)
         out["copy_probe"] = {"bytes_per_copy": 2 * src.numel() * 4, "ms": round(ms_copy, 5),
                              "gb_s": round(2 * src.numel() * 4 / (ms_copy * 1e-3) / 1e9, 1)}
-    want = {"c1", "c3", "c4", "c5", "g1", "g4", "sweep", "dims", "u1", "p1"} if args.rows == "all" else (set() if args.rows == "none" else set(args.rows.split(",")))
-    rows = {}
-    for name, fn in (("c1", row_c1), ("c4", row_c4), ("c3", row_c3), ("c5", row_c5), ("g1", row_g1), ("g4", row_g4), ("sweep", row_sweep), ("dims", row_dims), ("u1", row_u1), ("p1", row_p1)):
-        if name in want:
-            rows[name] = fn(svd, torch, synth, args)
-            print(f"row {name} done", file=sys.stderr, flush=True)
     if rows:
         out["rows"] = rows
     out["cpu_baseline"] = cpu
