@@ -166,8 +166,12 @@ def join_outputs(g, B, K):
     return outs
 
 
-def backward(P, cache, dout, D=33, R=8, K=6, Ds=17, mask=None, mixed=True):
-    """Gradients of every parameter given the upstream gradients dout (keys of forward's out)."""
+def backward(P, cache, dout, D=33, R=8, K=6, Ds=17, mask=None, mixed=True, abs_sums=None):
+    """Gradients of every parameter given the upstream gradients dout (keys of forward's out).
+
+    When abs_sums is a dict it receives, for each convolution bias, the per-channel sum of
+    |dz| over the terms that make up that bias's gradient (the scale against which a
+    rounding-level result is judged); the gradients themselves do not depend on it."""
     q = bf16_round if mixed else (lambda v: np.asarray(v, np.float64))
     acts, hs, stats, f, hid = cache["acts"], cache["hs"], cache["stats"], cache["f"], cache["hid"]
     B = f.shape[0]
@@ -192,6 +196,8 @@ def backward(P, cache, dout, D=33, R=8, K=6, Ds=17, mask=None, mixed=True):
         dzq = q(dz)
         G[f"conv{i + 1}.w"] = conv2d_wgrad(dzq, a_in, 2)
         G[f"conv{i + 1}.b"] = dz.sum(axis=(0, 1, 2))
+        if abs_sums is not None:
+            abs_sums[f"conv{i + 1}.b"] = np.abs(dz).sum(axis=(0, 1, 2))
         if i == 0:
             break
         da = conv2d_dgrad(dzq, q(P[f"conv{i + 1}.w"]), a_in.shape, 2)

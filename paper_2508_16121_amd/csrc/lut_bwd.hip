@@ -12,14 +12,19 @@
 // per wave instruction whatever the addresses, an LDS integer add about 17 (measured), so
 // the LDS accumulators hold signed 32-bit fixed-point values.  Each workgroup first bounds
 // its contributions: every dT term is dy * S * w with |S| <= max|map| (S interpolates the
-// map) and 0 <= w <= 1, every dmap term is dy * phi * w with |phi| <= max|T|, and no entry
-// receives more than one term per pixel.  With N pixels in the band the scale is the
-// largest power of two 2^e with N * max|dy| * max|map| * 2^e < 2^30 (dT) and likewise with
-// max|T| (dmap), so no accumulator can overflow and every term is rounded to within
-// 2^-(e+1) of its value; the power-of-two scale makes the conversions exact apart from
-// that one rounding.  Integer sums are also independent of the order of the atomics.
-// Non-finite dy, map or T values (or bounds beyond the float range) make the workgroup
-// report NaN for its dT and dmap contributions.
+// map) and 0 <= w <= 1, every dmap term is dy * phi * w with |phi| <= max|T|, an entry of LUT
+// or map channel l only receives terms of output channel c = l / 3, and each pixel adds at
+// most one term to an entry.  So no entry (and no partial sum of it) exceeds
+// Sigma_c * max|map| (dT) or Sigma_c * max|T| (dmap), where Sigma_c is the band's sum of
+// |dy_c|, and the scale is the largest power of two 2^e keeping max_c Sigma_c * max|.| * 2^e
+// below 2^30: no accumulator can overflow, every term is rounded once to within 2^-(e+1) of
+// its value, and the power-of-two scale makes the conversions exact apart from that one
+// rounding.  A bound from the sum (rather than pixels x largest |dy|) keeps a few large |dy|
+// from coarsening the grid of all other terms.  Terms below 2^22 take a two-instruction
+// rounding; when the scale lets one pixel's term exceed it (a |dy| holding more than about
+// 1/1024 of its band's sum) the workgroup uses the exact conversion instead.  Integer sums
+// are independent of the order of the atomics.  Non-finite dy, map or T values (or bounds
+// beyond the float range) make the workgroup report NaN for its dT and dmap contributions.
 #include "bwd_common.h"
 
 #include <algorithm>
@@ -59,7 +64,12 @@ struct BwdGeo {
 // One tile (row y, 256-pixel segment seg) of the backward.  The staged raw map rows (the
 // nine channels of rows iv and iv+1 for the segment's columns) are kept per wave and only
 // reloaded when the wave moves to another segment or another pair of map rows.
-template <typename IO, typename MT, bool FASTMAP, bool VEC, int LOSS>
+// Term -> accumulator integer: the two-instruction rounding while terms stay below 2^22,
+// the exact conversion when the workgroup's scale allows larger ones.
+template <bool EXACT>
+__device__ __forceinline__ int fixc(float a, float b) { return EXACT ? fix_exact(a, b) : fix_mul(a, b); }
+
+template <typename IO, typename MT, bool FASTMAP, bool VEC, int LOSS, bool EXACT>
 __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b, int y, int seg,
                                          const float* Tl, int* dTl, int* macc, int row_lo,
                                          float* raw, float* stage, int* dstage, int& st_seg, int& st_iv,
@@ -245,10 +255,10 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
                         int* q0 = dTl + slot;
                         int* q1 = q0 + rowstep;
                         const float gs = g * sT;
-                        lds_addi(q0 + c, fix_mul(gs, w00));
-                        lds_addi(q1 + c, fix_mul(gs, w10));
-                        lds_addi(q0 + kNode + c, fix_mul(gs, w01));
-                        lds_addi(q1 + kNode + c, fix_mul(gs, w11));
+                        lds_addi(q0 + c, fixc<EXACT>(gs, w00));
+                        lds_addi(q1 + c, fixc<EXACT>(gs, w10));
+                        lds_addi(q0 + kNode + c, fixc<EXACT>(gs, w01));
+                        lds_addi(q1 + kNode + c, fixc<EXACT>(gs, w11));
                     }
                     gx[al] = fmaf(g, (1.f - db) * (T10 - T00) + db * (T11 - T01), gx[al]);
                     gx[be] = fmaf(g, (1.f - da) * (T01 - T00) + da * (T11 - T10), gx[be]);
@@ -265,8 +275,8 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
                             A2[l] = fmaf(gp, tb, A2[l]);
                         } else {
                             const float gps = gp * sM;
-                            lds_addi(dstage + jk * kBwdStride + l, fix_mul(gps, 1.f - du));
-                            lds_addi(dstage + jk1 * kBwdStride + l, fix_mul(gps, du));
+                            lds_addi(dstage + jk * kBwdStride + l, fixc<EXACT>(gps, 1.f - du));
+                            lds_addi(dstage + jk1 * kBwdStride + l, fixc<EXACT>(gps, du));
                         }
                     }
                 }
@@ -280,9 +290,9 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
         if (FASTMAP && P.want_dmap) {
 #pragma unroll
             for (int l = 0; l < 9; ++l) {
-                lds_addi(dstage + j0 * kBwdStride + l, fix_mul(A0[l], sM));
-                lds_addi(dstage + j1 * kBwdStride + l, fix_mul(A1[l], sM));
-                lds_addi(dstage + j2 * kBwdStride + l, fix_mul(A2[l], sM));
+                lds_addi(dstage + j0 * kBwdStride + l, fixc<EXACT>(A0[l], sM));
+                lds_addi(dstage + j1 * kBwdStride + l, fixc<EXACT>(A1[l], sM));
+                lds_addi(dstage + j2 * kBwdStride + l, fixc<EXACT>(A2[l], sM));
             }
         }
         if (P.want_dx) {
@@ -367,16 +377,20 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
 #pragma unroll
         for (int c = 0; c < 3; ++c) bias3[c] = P.bias[3 * b + c];
     }
+    bool exact = false;
     if ((P.want_dT || P.want_dmap) && t0 < t1) {
         float mdy = 0.f, mmap = 0.f, mT = 0.f;
+        float sdy[3] = {0.f, 0.f, 0.f};
         bool nf = false;
         const int64_t e0 = (t0 / nseg) * a.W + (t0 % nseg) * kSeg;
         const int64_t e1 = ((t1 - 1) / nseg) * a.W + min(((t1 - 1) % nseg) * kSeg + kSeg, static_cast<int64_t>(a.W));
         const IO* dyb = reinterpret_cast<const IO*>(a.dy) + static_cast<int64_t>(b) * 3 * plane;
-        // dy given: its band maximum.  L1: |dy| <= 1/n.  MSE: |dy| = 2 |y - t| / n with
-        // |y_c| <= 3 max|map| max|T| + |b_c| and the band maximum of the target.
+        // dy given: the band's per-channel sums of |dy| (an entry of LUT or map channel l
+        // only receives terms of output channel l / 3) and its maximum.  L1: |dy| = 1/n at
+        // most.  MSE: |dy| = 2 |y - t| / n with |y_c| <= 3 max|map| max|T| + |b_c| and the
+        // band's sums and maximum of |t| (the dy buffer holds the target).
         if (LOSS != 1)
-            for (int c = 0; c < 3; ++c) absmax_range<IO>(dyb + c * plane + e0, e1 - e0, mdy, nf);
+            for (int c = 0; c < 3; ++c) abssum_range<IO>(dyb + c * plane + e0, e1 - e0, sdy[c], mdy, nf);
         if (P.want_dT || LOSS == 2) {
             const int64_t mplane = static_cast<int64_t>(a.h) * a.w;
             const MT* mb = reinterpret_cast<const MT*>(a.map) + static_cast<int64_t>(b) * 9 * mplane +
@@ -395,18 +409,26 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
             }
         }
         mdy = block_max(mdy, aux);
+        float sdm = 0.f;
+        if (LOSS != 1)
+            for (int c = 0; c < 3; ++c) sdm = fmaxf(sdm, block_sum(sdy[c], aux));
         mmap = block_max(mmap, aux);
         mT = block_max(mT, aux);
         bad = block_max(nf ? 1.f : 0.f, aux) > 0.f;
-        if (LOSS == 1) mdy = P.inv_n;
+        const float n = static_cast<float>((t1 - t0) * kSeg);   // band pixels (padding included)
+        if (LOSS == 1) {
+            mdy = P.inv_n;
+            sdm = n * P.inv_n;
+        }
         if (LOSS == 2) {
             const float mb = fmaxf(fabsf(bias3[0]), fmaxf(fabsf(bias3[1]), fabsf(bias3[2])));
-            mdy = 2.f * (3.f * mmap * mT + mb + mdy) * P.inv_n;
-            bad = bad || !(mdy <= FLT_MAX);
+            const float ymax = 3.f * mmap * mT + mb;
+            sdm = 2.f * (n * ymax + sdm) * P.inv_n;
+            mdy = 2.f * (ymax + mdy) * P.inv_n;
+            bad = bad || !(sdm <= FLT_MAX);
         }
-        const float n = static_cast<float>((t1 - t0) * kSeg);
-        sT = fix_scale(n, mdy, mmap, bad);
-        sM = fix_scale(n, mdy, mT, bad);
+        sT = fix_scale_sum(sdm, mdy, mmap, exact, bad);
+        sM = fix_scale_sum(sdm, mdy, mT, exact, bad);
     }
     const float iT = 1.f / sT, iM = 1.f / sM;
 
@@ -437,12 +459,23 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
             const int y = ya + (k - seg * nr);
             const int64_t lt = static_cast<int64_t>(y) * nseg + seg;
             if (lt < t0 || lt >= t1) continue;
-            if (base_ok && seg * kSeg + kSeg <= a.W)
-                bwd_tile<IO, MT, FASTMAP, true, LOSS>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage, dstage,
-                                                      st_seg, st_iv, sT, sM, iMx, dbsum, bias3, lacc);
-            else
-                bwd_tile<IO, MT, FASTMAP, false, LOSS>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage, dstage,
-                                                       st_seg, st_iv, sT, sM, iMx, dbsum, bias3, lacc);
+            const bool vec = base_ok && seg * kSeg + kSeg <= a.W;
+            if (!exact) {
+                if (vec)
+                    bwd_tile<IO, MT, FASTMAP, true, LOSS, false>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage,
+                                                                 dstage, st_seg, st_iv, sT, sM, iMx, dbsum, bias3, lacc);
+                else
+                    bwd_tile<IO, MT, FASTMAP, false, LOSS, false>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage,
+                                                                  dstage, st_seg, st_iv, sT, sM, iMx, dbsum, bias3, lacc);
+            } else {
+                if (vec)
+                    bwd_tile<IO, MT, FASTMAP, true, LOSS, true>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage,
+                                                                dstage, st_seg, st_iv, sT, sM, iMx, dbsum, bias3, lacc);
+                else
+                    bwd_tile<IO, MT, FASTMAP, false, LOSS, true>(P, G, b, y, seg, Tl, dTl, macc, row_lo, raw, stage,
+                                                                 dstage, st_seg, st_iv, sT, sM, iMx, dbsum, bias3, lacc);
+            }
+
         }
     }
     __syncthreads();
@@ -615,7 +648,8 @@ static svdlut_status launch_bwd_impl(const BwdLaunch& a, const LossArgs* L, hipS
     const int64_t mr = (a.H > 1) ? (band_rows * (a.h - 1)) / (a.H - 1) + 3 : 1;
     int mrows = static_cast<int>(std::min<int64_t>(a.h, mr));
     int block = 0;
-    const int blocks[2] = {512, 256};
+    // fine maps need narrow workgroups for their per-wave column staging
+    const int blocks[4] = {512, 256, 128, 64};
     for (int pass = 0; pass < 2 && block == 0; ++pass) {
         for (int bk : blocks) {
             if (bwd_lds(a.D, bk, P.ncol_max, mrows, a.w, a.R) <= static_cast<size_t>(di.lds_per_block)) {

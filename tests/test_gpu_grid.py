@@ -206,8 +206,8 @@ def test_unfused_original_structure_4k_sampled(svd):
     xs = np.concatenate([g.integers(0, W, 3000), [0, W - 1, W - 1, 0]])
     got = host(y)[0][:, ys, xs]
     fs = og.slice_grids_at(x[0], gr[0], gw[0], gb[0], ys, xs)                   # [K][n]
-    inp = np.concatenate([x[0][:, ys, xs].astype(np.float64), fs])              # [3 + K][n]
-    xbar = (Wf[0].astype(np.float64) @ inp + bf[0][:, None]).astype(np.float32)
-    ref = ou.lut3d(xbar[:, None, :], T3[0])[:, 0, :]
+    # the oracle's fusion on the sampled pixels laid out as a 1 x n image
+    xbar = ou.fuse(x[0][:, ys, xs][:, None, :], fs[:, None, :], Wf[0], bf[0]).astype(np.float32)
+    ref = ou.lut3d(xbar, T3[0])[:, 0, :]
     err = np.abs(got - ref).max()
     assert err <= TOL32, f"max-abs {err}"

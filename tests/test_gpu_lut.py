@@ -142,21 +142,24 @@ def test_apply_fp16_per_pixel_map(svd):
                      label="fp16 per-pixel map")
 
 
-def test_apply_4k_frame_sampled(svd):
-    """Full 3840x2160 frame, D=33 R=8, 270x480 map, float32: sampled rows/columns vs the oracle."""
+def test_apply_4k_frame_full(svd):
+    """Full 3840x2160 frame, D=33 R=8, 270x480 map, float32, in the launch configuration the
+    benchmark times: every pixel against the oracle (evaluated in row bands)."""
     c = synth.frame_4k()
     say("apply 4K frame")
     y = host(svd.apply(dev(c.x), dev(c.U), dev(c.s), dev(c.V), dev(c.smap)))[0]
-    T = ol.reconstruct(c.U, c.s, c.V)[0]
-    g = np.random.default_rng(22)
-    ys = np.concatenate([g.integers(0, 2160, 4000), [0, 2159, 0, 2159, 1080]])
-    xs = np.concatenate([g.integers(0, 3840, 4000), [0, 0, 3839, 3839, 255]])
-    ref = ol.transform_at(c.x[0], T, c.smap[0], ys, xs)
-    assert np.abs(y[:, ys, xs] - ref).max() <= TOL32
-    row = 1234
-    ref_row = ol.transform_at(c.x[0], T, c.smap[0], np.full(3840, row), np.arange(3840))
-    assert np.abs(y[:, row, :] - ref_row).max() <= TOL32
     assert np.isfinite(y).all()
+    T = ol.reconstruct(c.U, c.s, c.V)[0]
+    H, W = 2160, 3840
+    band = 120
+    worst = 0.0
+    for y0 in range(0, H, band):
+        ys = np.repeat(np.arange(y0, y0 + band), W)
+        xs = np.tile(np.arange(W), band)
+        ref = ol.transform_at(c.x[0], T, c.smap[0], ys, xs).reshape(3, band, W)
+        worst = max(worst, float(np.abs(y[:, y0:y0 + band] - ref).max()))
+    say(f"  4K max-abs {worst:.2e}")
+    assert worst <= TOL32
 
 
 def test_apply_is_deterministic(svd):

@@ -100,20 +100,50 @@ def test_paper_generator_forward_parity_4k_frame(PM):
         rel_close(got[k], ref[k], 2e-2, k)
 
 
-@pytest.mark.parametrize("K,use_mask", [(6, True), (0, False)])
-def test_paper_generator_backward_parity(PM, K, use_mask):
-    """Parameter gradients vs the bf16-mirror oracle.  The mirror cannot take every bf16
-    rounding and LeakyReLU branch decision the way the fp32-accumulating kernels do: a
-    decision that flips in an early block moves many later values by one bf16 step and
-    occasionally flips a LeakyReLU slope (1 vs 0.2) of one term.  The bar is therefore tied
-    to the size of the bf16 effect itself: for every tensor the GPU must be at most half as
-    far from the mirror as the mirror is from the exact fp64 network (relative Frobenius
-    norm), no element may be off by more than 15 % of the tensor's largest value, and the
-    FC-generator gradients, which see the convolutions only through the pooled features,
-    must agree to 2e-3.  A wrong index, sign, slope or dropped term moves a tensor by far
-    more than the bf16 effect (typically 5-50 % here)."""
-    say(f"paper generator backward K={K} mask={use_mask}")
-    P = rand_params(200 + K, K)
+def sign_stable_params(seed, K, sign):
+    """Parameters under which every convolution's pre-activation keeps one sign: input pixels
+    are >= 0, convolution weights are sign * |N(0, 2/fan)| and biases sign * U(0.05, 0.2),
+    and each instance norm maps to U(0.3, 0.5) * (standardised value) + U(3.5, 4.5), i.e. to
+    positive activations for the next convolution.  Every LeakyReLU then works on one branch
+    (slope 1 for sign +1, 0.2 for sign -1) and the norm variances are far above eps."""
+    g = np.random.default_rng(seed)
+    P = {}
+    for name, shp in pg.param_shapes(D, R, K, Ds):
+        if name.startswith("conv") and name.endswith(".w"):
+            P[name] = sign * np.abs(g.normal(0, np.sqrt(2.0 / np.prod(shp[1:])), shp))
+        elif name.startswith("conv") and name.endswith(".b"):
+            P[name] = sign * g.uniform(0.05, 0.2, shp)
+        elif name.endswith(".g"):
+            P[name] = g.uniform(0.3, 0.5, shp)
+        elif name.startswith("in") and name.endswith(".b"):
+            P[name] = g.uniform(3.5, 4.5, shp)
+        else:
+            P[name] = g.normal(0, 0.1, shp)
+    return P
+
+
+@pytest.mark.parametrize("K,use_mask,sign", [(6, True, 1.0), (6, True, -1.0), (0, False, 1.0), (0, False, -1.0)])
+def test_paper_generator_backward_parity(PM, K, use_mask, sign):
+    """Parameter gradients vs the bf16-mirror oracle with a fixed bar: every element within
+    3e-2 of its tensor's largest value (the FC generators within 2e-3), and a Frobenius
+    guard, GPU-to-mirror at most half of mirror-to-exact.
+
+    Derivation.  The kernels and the mirror round the same quantities to bf16 and take the
+    same LeakyReLU branch everywhere: the parameters keep every pre-activation on one side of
+    zero (checked below on the mirror, with a margin of 1 % of the block's largest value, far
+    above the bf16 step of the inputs).  What remains is the accumulation (fp32 on the GPU,
+    fp64 in the mirror, relative 1e-6) and the bf16 roundings that this moves across a
+    rounding boundary (a fraction of about 1e-6 / 2^-8 = 3e-4 of the stored values, each by
+    one bf16 step, 2^-8 relative).  A gradient element sums at least 64 products, so these
+    change it by well under 1e-3 of the tensor's scale: 3e-2 leaves a wide margin, while a
+    wrong index, sign, slope or dropped term moves a tensor by far more.  Both LeakyReLU
+    branches are covered, one per sign.  The biases of blocks 1-4 then have zero gradient
+    (checked as such, to 256 u of the sum of |terms|); their kernel is the one that gives
+    block 5's bias gradient (held to 3e-2 here), fed the same pre-activation gradient as the
+    block's weight gradient (also held to 3e-2), so no separate mixed-sign case with its
+    unstable branch decisions is needed for them."""
+    say(f"paper generator backward K={K} mask={use_mask} sign={sign:+.0f}")
+    P = sign_stable_params(200 + K + (sign < 0), K, sign)
     g = np.random.default_rng(201)
     B = 3
     x = g.uniform(0, 1, (B, 3, 256, 256)).astype(np.float32)
@@ -124,9 +154,12 @@ def test_paper_generator_backward_parity(PM, K, use_mask):
     up = {k: g.normal(0, 1, tuple(v.shape)).astype(np.float32) for k, v in o.items()}
     grads = gen.backward({k: torch.from_numpy(v).cuda() for k, v in up.items()}, mt)
     _, cache = pg.forward(P, x, D, R, K, Ds, mask=m, mixed=True)
+    for i, h in enumerate(cache["hs"]):          # the decisions are stable: one sign per block
+        assert (sign * h >= 1e-2 * np.abs(h).max()).all(), f"block {i + 1} has pre-activations near 0"
     up_o = dict(up)
     up_o["lut_w"] = up["lut_w"].reshape(B, 9)
-    ref = pg.backward(P, cache, up_o, D, R, K, Ds, mask=m, mixed=True)
+    l1 = {}
+    ref = pg.backward(P, cache, up_o, D, R, K, Ds, mask=m, mixed=True, abs_sums=l1)
     _, cache_x = pg.forward(P, x, D, R, K, Ds, mask=m, mixed=False)
     exact = pg.backward(P, cache_x, up_o, D, R, K, Ds, mask=m, mixed=False)
     got = pg.unflatten(host(grads), D, R, K, Ds)
@@ -134,11 +167,23 @@ def test_paper_generator_backward_parity(PM, K, use_mask):
         say(f"  {k:12s} gpu-mixed max {max_rel(got[k], ref[k]):.2e} fro {fro_rel(got[k], ref[k]):.2e} | "
             f"mixed-exact max {max_rel(ref[k], exact[k]):.2e} fro {fro_rel(ref[k], exact[k]):.2e}")
     for k in ref:
+        if k in ("conv1.b", "conv2.b", "conv3.b", "conv4.b"):
+            # With one LeakyReLU slope per channel the gradient of a bias in front of an
+            # instance norm is zero: dz = slope * dh and the norm's dh is mean-free per
+            # channel.  Both sides must give zero to rounding, judged per channel against
+            # L1 = sum |dz| over the summed terms.  The GPU's sum has depth <= 16 + 16 + the
+            # number of workgroups (< 200 here), and each fp32 term carries a relative error
+            # of a few u times (1 + |mean / std|) of the norm's input (< 20 here), so 256 u
+            # x L1 (u = 2^-24) is a safe bar; a gradient that is not mean-free is of the
+            # size of sqrt(sum dz^2) >= L1 / sqrt(terms), 300 times that bar or more here.
+            assert (np.abs(ref[k]) <= 1e-12 * l1[k]).all(), k
+            ratio = np.abs(got[k]) / l1[k]
+            say(f"  {k:12s} |gpu| / L1 max {ratio.max():.2e}")
+            assert (ratio <= 256 * 2.0 ** -24).all(), k
+            continue
+        assert max_rel(got[k], ref[k]) <= (3e-2 if k.startswith(("conv", "in")) else 2e-3), k
         f_gm, f_me = fro_rel(got[k], ref[k]), fro_rel(ref[k], exact[k])
-        assert f_gm <= max(0.5 * f_me, 1e-5), f"{k}: |gpu - mirror| {f_gm:.2e} vs |mirror - exact| {f_me:.2e}"
-        assert max_rel(got[k], ref[k]) <= 0.15, k
-        if not k.startswith(("conv", "in")):
-            assert max_rel(got[k], ref[k]) <= 2e-3, k
+        assert f_gm <= max(0.5 * f_me, 1e-4), f"{k}: |gpu - mirror| {f_gm:.2e} vs |mirror - exact| {f_me:.2e}"
 
 
 def test_paper_generator_missing_gradient_is_zero(PM):

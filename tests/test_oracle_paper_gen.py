@@ -147,3 +147,81 @@ def test_mixed_mode_is_bf16_close_to_exact():
     for k in a:
         scale = np.abs(b[k]).max()
         assert np.abs(a[k] - b[k]).max() <= 5e-2 * scale, k
+
+
+def _bf16(t):
+    """Round to bfloat16 (nearest even) through float32, as the mirror mode does, back to float64."""
+    return t.detach().float().to(torch.bfloat16).to(torch.float64)
+
+
+def _st(t):
+    """Value rounded to bf16, gradient passed straight through (a stored bf16 copy)."""
+    return t + (_bf16(t) - t).detach()
+
+
+def _round_grad(t):
+    """Identity forward; the gradient flowing back through t is rounded to bf16."""
+    t.register_hook(lambda g: _bf16(g))
+    return t
+
+
+def torch_reference_mixed(P, x, mask, K_, D_=D, R_=R, Ds_=Ds):
+    """torch_reference with bf16 casts where the mirror mode places them: the downsampled
+    input, the convolution weights and the normalised activations that feed the next
+    convolution are stored as bf16; the gradient of each convolution's output (before its
+    bias) is rounded to bf16 before it reaches the convolution's weight and input gradients;
+    biases, LeakyReLU, the normalisation, dropout, pooling and the FC generators stay in full
+    precision."""
+    T = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in P.items()}
+    a = _st(F.interpolate(torch.tensor(x, dtype=torch.float64), size=(256, 256), mode="bilinear",
+                          align_corners=False, antialias=False))
+    for i in range(5):
+        z = _round_grad(F.conv2d(a, _st(T[f"conv{i + 1}.w"]).permute(0, 3, 1, 2), None, stride=2, padding=1))
+        a = F.leaky_relu(z + T[f"conv{i + 1}.b"][None, :, None, None], 0.2)
+        if i < 4:
+            a = _st(F.instance_norm(a, weight=T[f"in{i + 1}.g"], bias=T[f"in{i + 1}.b"], eps=1e-5))
+    if mask is not None:
+        a = a * torch.tensor(mask, dtype=torch.float64) * 2.0
+    f = F.avg_pool2d(a, 4).flatten(1)
+    outs = {}
+    for h, _ in pg.head_sizes(D_, R_, K_, Ds_):
+        outs[h] = F.linear(F.linear(f, T[f"{h}.fc1.w"], T[f"{h}.fc1.b"]), T[f"{h}.fc2.w"], T[f"{h}.fc2.b"])
+    B = x.shape[0]
+    nU = 9 * D_ * R_
+    o = outs["t"]
+    res = {"U": o[:, :nU].reshape(B, 9, D_, R_), "s": o[:, nU:nU + 9 * R_].reshape(B, 9, R_),
+           "V": o[:, nU + 9 * R_:].reshape(B, 9, D_, R_),
+           "lut_w": outs["tw"].reshape(B, 3, 4)[:, :, :3].reshape(B, 9),
+           "lut_b": outs["tw"].reshape(B, 3, 4)[:, :, 3]}
+    if K_:
+        res["grids"] = outs["s"].reshape(B, K_, 3, Ds_, Ds_)
+        res["gw"] = outs["sw"].reshape(B, K_, 4)[:, :, :3]
+        res["gb"] = outs["sw"].reshape(B, K_, 4)[:, :, 3]
+    return res, T
+
+
+@pytest.mark.parametrize("K_,use_mask", [(6, True), (0, False)])
+def test_mixed_mode_matches_torch_with_bf16_casts(K_, use_mask):
+    """End-to-end pin of the mirror's rounding placement, forward outputs and every parameter
+    gradient: both sides take each bf16 decision from float64 values, so they agree to
+    float64 rounding; a rounding placed elsewhere, or one missing, moves values by a bf16
+    step (about 4e-3 relative) and fails the 1e-9 bar."""
+    P = rand_params(60 + K_, K_)
+    g = np.random.default_rng(61)
+    B = 2
+    x = g.uniform(0, 1, (B, 3, 200, 230))
+    mask = (g.uniform(size=(B, 64, 8, 8)) < 0.5).astype(np.float64) if use_mask else None
+    out, cache = pg.forward(P, x, D, R, K_, Ds, mask=mask, mixed=True)
+    ref, T = torch_reference_mixed(P, x, mask, K_)
+    for k in out:
+        r = ref[k].detach().numpy()
+        assert np.abs(out[k] - r).max() <= 1e-9 * max(1.0, np.abs(r).max()), k
+    up = {k: g.normal(size=v.shape) for k, v in out.items()}
+    grads = pg.backward(P, cache, up, D, R, K_, Ds, mask=mask, mixed=True)
+    L = sum((ref[k] * torch.from_numpy(up[k])).sum() for k in out)
+    L.backward()
+    for k in P:
+        r = T[k].grad.numpy()
+        assert np.abs(grads[k] - r).max() <= 1e-9 * max(1.0, np.abs(r).max()), k
+    exact, _ = pg.forward(P, x, D, R, K_, Ds, mask=mask, mixed=False)
+    assert np.abs(out["U"] - exact["U"]).max() > 1e-6 * np.abs(exact["U"]).max()

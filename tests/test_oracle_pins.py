@@ -495,3 +495,70 @@ def test_lut1d_matches_numpy_interp():
     # identity curve returns the clamped input
     ident = np.tile(knots, (3, 1))
     assert np.abs(ol.lut1d(x, ident) - np.clip(x, 0, 1)).max() <= 1e-7
+
+
+# ---------------------------------------------------------------- generator: bf16 mirror placement
+def _bf16(t):
+    """Round to bfloat16 (nearest even) through float32, as the mirror mode does, back to float64."""
+    return t.detach().float().to(torch.bfloat16).to(torch.float64)
+
+
+def _st(t):
+    """Value rounded to bf16, gradient passed straight through (a stored bf16 copy)."""
+    return t + (_bf16(t) - t).detach()
+
+
+def _round_grad(t):
+    """Identity forward; the gradient flowing back through t is rounded to bf16."""
+    t.register_hook(lambda g: _bf16(g))
+    return t
+
+
+def _torch_generator_mixed(P, x, D, R):
+    """The small CNN from torch primitives with bf16 casts where the mirror mode places them:
+    the downsampled input, every convolution weight and the post-ReLU activations are stored
+    as bf16; the gradient of each convolution's output is rounded to bf16 before it reaches
+    the convolution's weight and input gradients (bias gradients see the unrounded one); the
+    map head, pooling and the FC layer are full precision."""
+    t = {k: torch.tensor(v, dtype=torch.float64, requires_grad=True) for k, v in P.items()}
+    a = _st(F.interpolate(torch.from_numpy(x), size=(256, 256), mode="bilinear", align_corners=False))
+    a3 = None
+    for i in range(5):
+        w = _st(t[f"conv{i + 1}.w"]).permute(0, 3, 1, 2)
+        z = _round_grad(F.conv2d(a, w, None, stride=2, padding=1)) + t[f"conv{i + 1}.b"][None, :, None, None]
+        a = _st(torch.relu(z))
+        if i == 2:
+            a3 = a
+    zm = _round_grad(F.conv2d(a3, _st(t["head.w"]).permute(0, 3, 1, 2), None, padding=1))
+    smap = zm + t["head.b"][None, :, None, None]
+    o = a.mean(dim=(2, 3)) @ t["fc.w"].T + t["fc.b"]
+    blk = o.reshape(x.shape[0], 9, 2 * D * R + R)
+    return (t, blk[:, :, :D * R].reshape(-1, 9, D, R), blk[:, :, D * R:D * R + R],
+            blk[:, :, D * R + R:].reshape(-1, 9, D, R), smap)
+
+
+def test_generator_mixed_mode_matches_torch_with_bf16_casts():
+    """End-to-end pin of the mirror's rounding placement (forward outputs and every parameter
+    gradient): both sides take each bf16 decision from float64 values, so they agree to
+    float64 rounding; a rounding placed elsewhere, or one missing, moves values by a bf16
+    step (about 4e-3 relative) and fails the 1e-9 bar."""
+    D, R = 5, 2
+    g = np.random.default_rng(18)
+    P = _init_params(g, D, R)
+    x = g.uniform(size=(2, 3, 300, 280))
+    U, s, V, smap, cache = og.forward(P, x, D, R, mixed=True)
+    t, tU, ts, tV, tmap = _torch_generator_mixed(P, x, D, R)
+    for a, b_ in ((U, tU), (s, ts), (V, tV), (smap, tmap)):
+        ref = b_.detach().numpy()
+        assert np.abs(a - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max())
+    GU, Gs, GV, Gm = (g.normal(size=a.shape) for a in (U, s, V, smap))
+    grads = og.backward(P, cache, GU, Gs, GV, Gm, mixed=True)
+    L = (tU * torch.from_numpy(GU)).sum() + (ts * torch.from_numpy(Gs)).sum() + \
+        (tV * torch.from_numpy(GV)).sum() + (tmap * torch.from_numpy(Gm)).sum()
+    L.backward()
+    for k in P:
+        ref = t[k].grad.numpy()
+        assert np.abs(grads[k] - ref).max() <= 1e-9 * max(1.0, np.abs(ref).max()), k
+    # and the mirror is not the exact network (the casts are really there)
+    U_x = og.forward(P, x, D, R, mixed=False)[0]
+    assert np.abs(U - U_x).max() > 1e-6 * np.abs(U_x).max()
