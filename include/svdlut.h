@@ -146,9 +146,28 @@ svdlut_status svdlut_unfused_apply(const float* x, float* y, const float* grids,
  *   aligned, owned by the caller; contents on entry are ignored.
  * dT is accumulated in fixed point per workgroup and summed in a fixed order, so dU, ds
  * and dV are reproducible, as is dx; dmap and dbias are summed across workgroups with
- * float atomics and depend on their order at the level of float32 rounding.
+ * float atomics and depend on their order at the level of float32 rounding, except in
+ * deterministic mode (svdlut_set_deterministic), where they are bitwise reproducible too.
  */
 size_t svdlut_apply_bwd_workspace_size(int32_t B, int32_t D);
+
+/*
+ * Deterministic mode (process-wide; initially on when the environment variable
+ * SVDLUT_DETERMINISTIC is set to a non-empty value other than "0").  In this mode the
+ * backward entry points (svdlut_apply_bwd, _noalloc, svdlut_apply_grid_bwd,
+ * svdlut_apply_loss_bwd) reduce dmap and dbias from per-workgroup partials in a fixed order
+ * instead of float atomics, so every output is bitwise reproducible for the same inputs on
+ * the same device.  It needs svdlut_deterministic_workspace_size(B, H, W, h, w) more bytes of
+ * workspace, placed after the entry point's usual size rounded up to 256 bytes (the whole
+ * workspace is then that rounded size plus this), whenever dmap or dbias is requested (a
+ * workspace becomes required then even without dU); a shorter one gives EINVAL.  A map whose
+ * map-row accumulator does not fit the LDS (very wide maps) gives EUNSUPPORTED in this mode.
+ * The generators' backward passes are reproducible in both modes.  The setter may be called
+ * at any time between calls; calls already queued keep the mode they were issued with.
+ */
+void svdlut_set_deterministic(int32_t on);
+int32_t svdlut_get_deterministic(void);
+size_t svdlut_deterministic_workspace_size(int32_t B, int32_t H, int32_t W, int32_t h, int32_t w);
 svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io,
                                const float* U, const float* s, const float* V,
                                const void* map, svdlut_dtype map_dt,
@@ -169,8 +188,9 @@ svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io,
  * (two streams, two host threads) race and must be serialised by the caller.
  * Errors: those of svdlut_apply_bwd, plus EINVAL when the factor gradients are requested
  * and svdlut_apply_bwd_workspace_size(B, D) exceeds SVDLUT_NOALLOC_SCRATCH_BYTES (e.g. at
- * D = 40 up to B = 369 fits, at D = 33 up to B = 577), and EDEVICE if the buffer's address
- * cannot be obtained.
+ * D = 40 up to B = 369 fits, at D = 33 up to B = 577), or in deterministic mode when that
+ * size rounded up to 256 bytes plus svdlut_deterministic_workspace_size(B, H, W, h, w)
+ * exceeds it, and EDEVICE if the buffer's address cannot be obtained.
  */
 #define SVDLUT_NOALLOC_SCRATCH_BYTES (24u * 1024u * 1024u)
 svdlut_status svdlut_apply_bwd_noalloc(const void* x, const void* dy, svdlut_dtype io,
@@ -311,7 +331,7 @@ svdlut_status svdlut_apply_loss_bwd(const void* x, const void* target, svdlut_dt
  *   must share ws and the parameters must not change between them.
  * Forward outputs: U, V [B][9][D][R], s [B][9][R], map [B][9][32][32], float32.
  * Backward inputs dU, ds, dV, dmap have the same shapes; grads (out) has the layout of
- * params.
+ * params.  Forward and backward are deterministic (fixed-order reductions throughout).
  */
 size_t svdlut_generator_param_count(int32_t D, int32_t R);
 size_t svdlut_generator_workspace_size(int32_t B, int32_t D, int32_t R);
@@ -357,9 +377,9 @@ svdlut_status svdlut_generator_bwd(const float* params, const float* dU, const f
  *   K = 0).  Backward inputs have the same shapes; a NULL gradient counts as zero.  grads
  *   (out) has the layout of params and is overwritten.
  * K in [0, 12]; Ds in [2, 33] when K > 0; D in [2, 40]; R in [1, 64].
- * The forward is deterministic (fixed-order reductions).  In the backward, convolution and FC
- * weight gradients are reproducible; convolution biases and norm scale/shift gradients are
- * summed with float atomics and may differ in the last bits between runs.
+ * The forward and the backward are deterministic: every reduction (weights, biases, norm
+ * scale and shift, FC layers) adds per-workgroup partials in a fixed order, so the same
+ * inputs give bitwise the same outputs and gradients on the same device.
  */
 size_t svdlut_paper_generator_param_count(int32_t D, int32_t R, int32_t K, int32_t Ds);
 size_t svdlut_paper_generator_workspace_size(int32_t B, int32_t D, int32_t R, int32_t K, int32_t Ds);

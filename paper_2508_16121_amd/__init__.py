@@ -8,8 +8,8 @@ from ._lib import SvdlutError, load as _load_lib
 
 _load_lib()
 
-from .ops import apply, apply_autograd, apply_loss_bwd, loss_bwd_workspace, apply_grid, apply_grid_bwd, apply_bwd, bwd_workspace, grid_bwd_workspace, loss, lut1d_apply, lut3d_apply, reconstruct, unfused_apply  # noqa: E402
+from .ops import apply, apply_autograd, deterministic, apply_loss_bwd, loss_bwd_workspace, apply_grid, apply_grid_bwd, apply_bwd, bwd_workspace, grid_bwd_workspace, loss, lut1d_apply, lut3d_apply, reconstruct, unfused_apply  # noqa: E402
 from .plan import Plan, pack_offsets  # noqa: E402
 
-__all__ = ["apply", "apply_autograd", "apply_loss_bwd", "loss_bwd_workspace", "apply_grid", "apply_grid_bwd", "apply_bwd", "bwd_workspace", "grid_bwd_workspace", "loss", "lut1d_apply", "lut3d_apply", "reconstruct", "unfused_apply", "Plan",
+__all__ = ["apply", "apply_autograd", "deterministic", "apply_loss_bwd", "loss_bwd_workspace", "apply_grid", "apply_grid_bwd", "apply_bwd", "bwd_workspace", "grid_bwd_workspace", "loss", "lut1d_apply", "lut3d_apply", "reconstruct", "unfused_apply", "Plan",
            "pack_offsets", "SvdlutError"]

@@ -41,6 +41,9 @@ SIGS = {
                                I32, I32, I32, I32, I32, I32, I32, P, SZ, P]),
     "svdlut_apply_bwd_noalloc": (I32, [P, P, I32, P, P, P, P, I32, P, P, P, P, P, P,
                                        I32, I32, I32, I32, I32, I32, I32, P]),
+    "svdlut_set_deterministic": (None, [I32]),
+    "svdlut_get_deterministic": (I32, []),
+    "svdlut_deterministic_workspace_size": (SZ, [I32, I32, I32, I32, I32]),
     "svdlut_plan_create": (I32, [P, I32, I32, I32, I32, I32, P]),
     "svdlut_plan_autotune": (I32, [P, P, P, P, P, P, P, P, P]),
     "svdlut_plan_launch": (I32, [P, P, P, P, P, P, P, P, P]),

@@ -1,8 +1,10 @@
 // extern "C" entry points of the 2D-LUT path: argument validation (before any HIP call),
 // launch configuration, error reporting, and the uneven-batch plan (HIP graph + tuner).
 #include "internal.h"
+#include "tune_cache.h"
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
@@ -54,6 +56,24 @@ const DeviceInfo& device_info() {
 }
 
 size_t bwd_workspace_bytes(int B, int D);
+
+// ---------------------------------------------------------------- deterministic mode
+// -1 until first read: then the environment variable SVDLUT_DETERMINISTIC (set, non-empty
+// and not "0" turns it on), unless svdlut_set_deterministic chose first.
+static std::atomic<int> g_det{-1};
+
+bool deterministic_mode() {
+    int v = g_det.load(std::memory_order_relaxed);
+    if (v < 0) {
+        const char* e = std::getenv("SVDLUT_DETERMINISTIC");
+        int want = (e && *e && std::strcmp(e, "0") != 0) ? 1 : 0;
+        g_det.compare_exchange_strong(v, want);
+        v = g_det.load(std::memory_order_relaxed);
+    }
+    return v == 1;
+}
+
+static size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
 // ---------------------------------------------------------------- validation helpers
 static bool dims_ok(int64_t v) { return v >= 1 && v <= kMaxDim; }
@@ -110,17 +130,33 @@ static svdlut_status check_apply_bwd(const void* x, const void* dy, svdlut_dtype
     return check_lut_dims(D, R);
 }
 
-// The backward launch once the arguments (and the partial buffer ws) are settled.
+// Deterministic mode: whether a backward call needs the partials region (dmap or dbias
+// requested), and where it sits: after the first `base` bytes of the workspace, aligned.
+static bool det_needed(const float* dmap, const float* dbias) { return (dmap || dbias) && deterministic_mode(); }
+
+static svdlut_status det_region(void* ws, size_t ws_bytes, size_t base, int32_t B, int32_t H, int32_t W, int32_t h,
+                                int32_t w, const char* what, void** det) {
+    const size_t need = align256(base) + bwd_det_bytes(B, H, W, h, w);
+    if (!ws || ws_bytes < need)
+        return fail(SVDLUT_EINVAL, std::string(what) + ": deterministic mode needs a workspace of " +
+                                       std::to_string(need) + " bytes (the usual size plus "
+                                       "svdlut_deterministic_workspace_size())");
+    *det = static_cast<char*>(ws) + align256(base);
+    return SVDLUT_OK;
+}
+
+// The backward launch once the arguments (and the partial buffers) are settled.
 static svdlut_status apply_bwd_launch(const void* x, const void* dy, svdlut_dtype io, const float* U, const float* s,
                                       const float* V, const void* map, svdlut_dtype map_dt, void* dx, float* dU,
                                       float* ds, float* dV, float* dmap, float* dbias, int32_t B, int32_t H,
                                       int32_t W, int32_t h, int32_t w, int32_t D, int32_t R, void* ws,
-                                      hipStream_t stream) {
+                                      void* det, hipStream_t stream) {
     if (!dx && !dU && !dmap && !dbias) return SVDLUT_OK;
     BwdLaunch a{};
     a.x = x; a.dy = dy; a.U = U; a.s = s; a.V = V; a.map = map;
     a.dx = dx; a.dU = dU; a.ds = ds; a.dV = dV; a.dmap = dmap; a.dbias = dbias;
     a.dT = static_cast<float*>(ws);
+    a.det = det;
     a.B = B; a.H = H; a.W = W; a.h = h; a.w = w; a.D = D; a.R = R;
     a.io = io; a.map_dt = map_dt;
     return launch_apply_bwd(a, stream);
@@ -307,9 +343,14 @@ svdlut_status svdlut_apply_grid_bwd(const void* x, const void* dy, svdlut_dtype 
     const size_t lut_ws = (bwd_workspace_bytes(B, D) + 255) & ~static_cast<size_t>(255);
     if ((ng == 3 || dU) && (!ws || ws_bytes < lut_ws + grid_bwd_workspace_bytes(B, Ds)))
         return fail(SVDLUT_EINVAL, "apply_grid_bwd: workspace smaller than svdlut_apply_grid_bwd_workspace_size()");
+    SVDLUT_TRY(check_apply_bwd(x, dy, io, U, s, V, map, map_dt, dU, ds, dV, B, H, W, h, w, D, R));
+    void* det = nullptr;
+    if (det_needed(dmap, dbias))
+        SVDLUT_TRY(det_region(ws, ws_bytes, lut_ws + grid_bwd_workspace_bytes(B, Ds), B, H, W, h, w,
+                              "apply_grid_bwd", &det));
     // the LUT part writes dx (and the LUT gradients); the grid part then adds into dx
-    SVDLUT_TRY(svdlut_apply_bwd(x, dy, io, U, s, V, map, map_dt, dx, dU, ds, dV, dmap, dbias, B, H, W, h,
-                                w, D, R, ws, ws_bytes, stream));
+    SVDLUT_TRY(apply_bwd_launch(x, dy, io, U, s, V, map, map_dt, dx, dU, ds, dV, dmap, dbias, B, H, W, h, w, D, R,
+                                ws, det, stream));
     GridBwdLaunch g{};
     g.x = x; g.dy = dy; g.dx = dx; g.grids = grids; g.gw = gw;
     g.part = ws ? reinterpret_cast<float*>(static_cast<char*>(ws) + lut_ws) : nullptr;
@@ -335,8 +376,11 @@ svdlut_status svdlut_apply_bwd(const void* x, const void* dy, svdlut_dtype io, c
         if (ws_bytes < bwd_workspace_bytes(B, D))
             return fail(SVDLUT_EINVAL, "apply_bwd: workspace smaller than svdlut_apply_bwd_workspace_size()");
     }
+    void* det = nullptr;
+    if (det_needed(dmap, dbias))
+        SVDLUT_TRY(det_region(ws, ws_bytes, bwd_workspace_bytes(B, D), B, H, W, h, w, "apply_bwd", &det));
     return apply_bwd_launch(x, dy, io, U, s, V, map, map_dt, dx, dU, ds, dV, dmap, dbias, B, H, W, h, w, D, R,
-                            ws, stream);
+                            ws, det, stream);
 }
 
 svdlut_status svdlut_apply_bwd_noalloc(const void* x, const void* dy, svdlut_dtype io, const float* U,
@@ -346,18 +390,32 @@ svdlut_status svdlut_apply_bwd_noalloc(const void* x, const void* dy, svdlut_dty
                                        int32_t R, hipStream_t stream) {
     SVDLUT_TRY(check_apply_bwd(x, dy, io, U, s, V, map, map_dt, dU, ds, dV, B, H, W, h, w, D, R));
     const bool factors = dU != nullptr;
+    const bool det = det_needed(dmap, dbias);
     void* ws = nullptr;
-    if (factors) {
-        const size_t need = bwd_workspace_bytes(B, D);
+    void* det_ptr = nullptr;
+    if (factors || det) {
+        // the dT partials first, then (deterministic mode) the dmap and dbias partials
+        const size_t need = det ? align256(bwd_workspace_bytes(B, D)) + bwd_det_bytes(B, H, W, h, w)
+                                : bwd_workspace_bytes(B, D);
         if (need > static_cast<size_t>(SVDLUT_NOALLOC_SCRATCH_BYTES))
             return fail(SVDLUT_EINVAL, "apply_bwd_noalloc: B = " + std::to_string(B) + ", D = " + std::to_string(D) +
-                                           " needs " + std::to_string(need) +
+                                           (det ? " (deterministic mode)" : "") + " needs " + std::to_string(need) +
                                            " bytes of scratch, more than the library's " +
                                            std::to_string(static_cast<size_t>(SVDLUT_NOALLOC_SCRATCH_BYTES)));
         SVDLUT_TRY(scratch_for_current_device(&ws));
+        if (det) det_ptr = static_cast<char*>(ws) + align256(bwd_workspace_bytes(B, D));
     }
     return apply_bwd_launch(x, dy, io, U, s, V, map, map_dt, dx, dU, ds, dV, dmap, dbias, B, H, W, h, w, D, R,
-                            ws, stream);
+                            factors ? ws : nullptr, det_ptr, stream);
+}
+
+void svdlut_set_deterministic(int32_t on) { g_det.store(on ? 1 : 0); }
+
+int32_t svdlut_get_deterministic(void) { return deterministic_mode() ? 1 : 0; }
+
+size_t svdlut_deterministic_workspace_size(int32_t B, int32_t H, int32_t W, int32_t h, int32_t w) {
+    if (B < 1 || !dims_ok(H) || !dims_ok(W) || !dims_ok(h) || !dims_ok(w)) return 0;
+    return bwd_det_bytes(B, H, W, h, w);
 }
 
 }  // extern "C"
@@ -387,7 +445,7 @@ struct svdlut_plan {
 namespace svdlut {
 
 static std::mutex g_tune_mu;
-static std::map<std::string, std::pair<int, int>> g_tune;   // key -> (block, blocks per CU)
+static std::map<std::string, TuneEntry> g_tune;   // problem class -> workgroup shape
 static bool g_tune_loaded = false;
 
 static std::string tune_key(const svdlut_plan* p, const DeviceInfo& di) {
@@ -400,7 +458,8 @@ static std::string tune_key(const svdlut_plan* p, const DeviceInfo& di) {
     return os.str();
 }
 
-// The cache file is a flat JSON object {"key": [block, blocks_per_cu], ...}.
+// The cache file (JSON, see tune_cache.h) named by SVDLUT_TUNE_CACHE is read once; a
+// missing, unreadable or corrupt file leaves the built-in defaults for what it lacks.
 static void tune_load_locked() {
     if (g_tune_loaded) return;
     g_tune_loaded = true;
@@ -410,24 +469,7 @@ static void tune_load_locked() {
     if (!f) return;
     std::stringstream ss;
     ss << f.rdbuf();
-    const std::string txt = ss.str();
-    size_t pos = 0;
-    while (true) {
-        const size_t k0 = txt.find('"', pos);
-        if (k0 == std::string::npos) break;
-        const size_t k1 = txt.find('"', k0 + 1);
-        if (k1 == std::string::npos) break;
-        const size_t b0 = txt.find('[', k1);
-        const size_t b1 = txt.find(']', b0 == std::string::npos ? k1 : b0);
-        if (b0 == std::string::npos || b1 == std::string::npos) break;
-        int blk = 0, bpc = 0;
-        if (std::sscanf(txt.c_str() + b0, "[%d , %d]", &blk, &bpc) == 2 ||
-            std::sscanf(txt.c_str() + b0, "[%d,%d]", &blk, &bpc) == 2) {
-            if ((blk == 64 || blk == 128 || blk == 256 || blk == 512 || blk == 1024) && bpc >= 1 && bpc <= 32)
-                g_tune[txt.substr(k0 + 1, k1 - k0 - 1)] = {blk, bpc};
-        }
-        pos = b1 + 1;
-    }
+    parse_tune_cache(ss.str(), g_tune);
 }
 
 static void tune_save_locked() {
@@ -435,13 +477,7 @@ static void tune_save_locked() {
     if (!path) return;
     std::ofstream f(path);
     if (!f) return;
-    f << "{\n";
-    size_t i = 0;
-    for (const auto& kv : g_tune) {
-        f << "  \"" << kv.first << "\": [" << kv.second.first << ", " << kv.second.second << "]"
-          << (++i < g_tune.size() ? "," : "") << "\n";
-    }
-    f << "}\n";
+    f << format_tune_cache(g_tune);
 }
 
 static ApplyLaunch plan_args(const svdlut_plan* p, const void* x, void* y, const float* U, const float* s,
@@ -556,9 +592,9 @@ svdlut_status svdlut_plan_create(const svdlut_image_desc* descs, int32_t B, int3
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
-        if (it != g_tune.end() && it->second.first <= maxb &&
-            apply_lds_bytes(D, R, it->second.first, p->ncol_max) <= static_cast<size_t>(di.lds_per_block)) {
-            plan_set_shape(p, it->second.first, it->second.second, di);
+        if (it != g_tune.end() && it->second.block <= maxb &&
+            apply_lds_bytes(D, R, it->second.block, p->ncol_max) <= static_cast<size_t>(di.lds_per_block)) {
+            plan_set_shape(p, it->second.block, it->second.bpc, di);
             p->tuned = 1;
         }
     }
@@ -679,7 +715,7 @@ svdlut_status svdlut_plan_autotune(svdlut_plan* p, const void* x, void* y, const
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
-        g_tune[tune_key(p, di)] = {bestc.block, bestc.bpc};
+        g_tune[tune_key(p, di)] = TuneEntry{bestc.block, bestc.bpc};
         tune_save_locked();
     }
     plan_drop_graph(p);

@@ -337,29 +337,40 @@ __global__ void downsample_kernel(const IO* __restrict__ x, uint16_t* __restrict
     }
 }
 
-// Bias gradient: db[co] += sum of dz(m, co) over a chunk of output pixels.  256 threads:
-// thread t takes channel t % Co and pixel lane t / Co (256 / Co lanes, 16 pixels each); the
-// lanes of a channel are added in LDS and one atomic per channel and workgroup remains.
+// Bias gradient db[co] = sum of dz(m, co) over the output pixels, in a fixed order.  256
+// threads: thread t takes channel t % Co and pixel lane t / Co (256 / Co lanes, 16 pixels
+// each); workgroup g takes chunks g, g + G, ... of nl * 16 pixels, adds its lanes in LDS and
+// stores one partial per channel; bias_sum_kernel adds the G partials in workgroup order.
 constexpr int kBiasPx = 16;
+constexpr int kBiasGroups = 256;
 
 inline int bias_lanes(int Co) { return std::max(1, 256 / Co); }
 
 template <class DZ>
-__global__ void __launch_bounds__(256) bias_grad_kernel(DZ dz, float* __restrict__ db, int M, int Co) {
+__global__ void __launch_bounds__(256) bias_grad_kernel(DZ dz, float* __restrict__ part, int M, int Co) {
     __shared__ float red[256];
     const int t = threadIdx.x, nl = max(1, 256 / Co);
     const int co = t % Co, lane = t / Co;
-    const int m0 = blockIdx.x * nl * kBiasPx;
+    const int chunk = nl * kBiasPx;
     float acc = 0.f;
     if (lane < nl && t < Co * nl)
-        for (int m = m0 + lane; m < min(M, m0 + nl * kBiasPx); m += nl) acc += dz(m, co);
+        for (int m0 = blockIdx.x * chunk; m0 < M; m0 += gridDim.x * chunk)
+            for (int m = m0 + lane; m < min(M, m0 + chunk); m += nl) acc += dz(m, co);
     red[t] = acc;
     __syncthreads();
     if (t < Co) {
         float s = 0.f;
         for (int l = 0; l < nl; ++l) s += red[l * Co + t];
-        __hip_atomic_fetch_add(db + t, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        part[static_cast<int64_t>(blockIdx.x) * Co + t] = s;
     }
+}
+
+__global__ void bias_sum_kernel(const float* __restrict__ part, int groups, int Co, float* __restrict__ db) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= Co) return;
+    float s = 0.f;
+    for (int g = 0; g < groups; ++g) s += part[static_cast<int64_t>(g) * Co + t];
+    db[t] = s;
 }
 
 // dW[co][tap][ci] = sum over the split-K slices of part[z][co][tap * Cs + ci]: one wave per
@@ -443,9 +454,13 @@ void conv_backward(const ConvGeo& g, DZ dz, const uint16_t* in, const float* w, 
     gemm<4>(WgradA<DZ>{dz, g}, WgradB{in, g}, EpiPartial{wpart, g.Co, N}, g.Co, N, Mo, sk, st);
     hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((g.Co * N + 3) / 4), dim3(256), 0, st, wpart,
                        gemm_slices(Mo, sk), dw, g.Co, g.Ci, g.Cs);
+    // the weight-gradient partials are consumed by now: wpart takes the bias partials
     const int px_per_wg = bias_lanes(g.Co) * kBiasPx;
-    hipLaunchKernelGGL(bias_grad_kernel<DZ>, dim3((Mo + px_per_wg - 1) / px_per_wg), dim3(256), 0, st, dz, db, Mo,
-                       g.Co);
+    const int groups = static_cast<int>(std::max<size_t>(
+        1, std::min<size_t>({static_cast<size_t>((Mo + px_per_wg - 1) / px_per_wg), static_cast<size_t>(kBiasGroups),
+                             wgrad_part_floats(g) / g.Co})));
+    hipLaunchKernelGGL(bias_grad_kernel<DZ>, dim3(groups), dim3(256), 0, st, dz, wpart, Mo, g.Co);
+    hipLaunchKernelGGL(bias_sum_kernel, dim3((g.Co + 63) / 64), dim3(64), 0, st, wpart, groups, g.Co, db);
     if (da_in) {
         const int Mi = g.N * g.Hi * g.Wi;
         gemm_nt(g.Ci, DgradA<DZ>{dz, g}, DgradB{w, g}, EpiStore{da_in, Mi, g.Cs, accumulate_da}, Mi,

@@ -92,12 +92,17 @@ struct BwdLaunch {
     float* dmap;
     float* dbias;
     float* dT;                     // workspace [B][9][D][D]
+    // deterministic mode: per-workgroup dmap and dbias partials, bwd_det_bytes(B, H, W, h, w)
+    // bytes, summed in a fixed order by a second kernel (nullptr: float atomics)
+    void* det;
     int32_t B, H, W, h, w, D, R;
     svdlut_dtype io, map_dt;
 };
 svdlut_status launch_apply_bwd(const BwdLaunch& a, hipStream_t st);
 int bwd_groups_per_image(int B);
 size_t bwd_workspace_bytes(int B, int D);
+size_t bwd_det_bytes(int B, int H, int W, int h, int w);
+bool deterministic_mode();
 
 // Backward of the bilateral-grid slicing; dx (if set) is accumulated into.
 struct GridBwdLaunch {

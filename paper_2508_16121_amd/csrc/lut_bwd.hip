@@ -52,6 +52,12 @@ struct BwdDev {
     const float* bias;  // forward bias [B][3] (nullable)
     float inv_n;        // 1 / (B * 3 * H * W)
     float* lpart;       // per-workgroup loss partial sums [B * gpi]
+    // deterministic mode (rowlo non-null): each workgroup stores its first map row, its dbias
+    // partial and its map-row accumulator as floats; det_reduce_kernel adds them up in
+    // workgroup order instead of float atomics
+    int* rowlo;         // [B * gpi]
+    float* dbpart;      // [B * gpi][3]
+    float* mpart;       // [B * gpi][9][mrows][w]
 };
 
 // Geometry shared by all tiles of a workgroup.
@@ -485,7 +491,12 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
         for (int e = threadIdx.x; e < nlut; e += blockDim.x)
             part[e] = bad ? __builtin_nanf("") : static_cast<float>(dTl[e]) * iT;
     }
-    if (P.want_dmap && P.mrows > 0 && t0 < t1) {
+    if (P.rowlo && threadIdx.x == 0) P.rowlo[lb] = t0 < t1 ? row_lo : a.h;   // a.h: no rows
+    if (P.want_dmap && P.mpart && t0 < t1) {
+        float* dst = P.mpart + static_cast<size_t>(lb) * macc_n;
+        for (int e = threadIdx.x; e < macc_n; e += blockDim.x)
+            dst[e] = bad ? __builtin_nanf("") : static_cast<float>(macc[e]) * iM;
+    } else if (P.want_dmap && P.mrows > 0 && t0 < t1) {
         const int64_t mplane = static_cast<int64_t>(a.h) * a.w;
         for (int e = threadIdx.x; e < macc_n; e += blockDim.x) {
             const int l = e / (P.mrows * a.w);
@@ -500,11 +511,24 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
         }
     }
     if (P.want_db) {
+        __shared__ float dbw[3][1024 / kWave];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             float v = dbsum[c];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if ((threadIdx.x & 63) == 0) gbl_add(a.dbias + 3 * b + c, v);
+            if (P.dbpart) {
+                if ((threadIdx.x & 63) == 0) dbw[c][wave] = v;
+            } else if ((threadIdx.x & 63) == 0) {
+                gbl_add(a.dbias + 3 * b + c, v);
+            }
+        }
+        if (P.dbpart) {
+            __syncthreads();
+            if (threadIdx.x < 3) {      // the waves' sums in wave order
+                float v = 0.f;
+                for (int i = 0; i < nw; ++i) v += dbw[threadIdx.x][i];
+                P.dbpart[3 * lb + threadIdx.x] = v;
+            }
         }
     }
     if (LOSS) {
@@ -526,6 +550,41 @@ __global__ void loss_sum_kernel(const float* __restrict__ part, int n, float inv
     for (int i = threadIdx.x; i < n; i += 64) acc += part[i];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
     if (threadIdx.x == 0) out[0] = static_cast<float>(acc * static_cast<double>(inv_n));
+}
+
+// Deterministic mode: dmap and dbias from the per-workgroup partials, added in workgroup
+// order.  The workgroups of an image cover consecutive bands, so their first map rows rowlo
+// do not decrease with the workgroup index; the ones whose accumulator [rowlo, rowlo + mrows)
+// holds row r form a run found by a binary search.  Workgroups without rows carry rowlo = h.
+__global__ void __launch_bounds__(256) det_reduce_kernel(const int* __restrict__ rowlo,
+                                                         const float* __restrict__ mpart,
+                                                         const float* __restrict__ dbpart, float* __restrict__ dmap,
+                                                         float* __restrict__ dbias, int B, int gpi, int mrows, int h,
+                                                         int w) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t nmap = dmap ? static_cast<int64_t>(B) * 9 * h * w : 0;
+    if (i < nmap) {
+        const int col = static_cast<int>(i % w);
+        const int r = static_cast<int>((i / w) % h);
+        const int l = static_cast<int>((i / (static_cast<int64_t>(w) * h)) % 9);
+        const int b = static_cast<int>(i / (static_cast<int64_t>(w) * h * 9));
+        const int* rl = rowlo + static_cast<int64_t>(b) * gpi;
+        int lo = 0, hi = gpi;           // first j with rl[j] + mrows > r
+        while (lo < hi) {
+            const int mid = (lo + hi) >> 1;
+            if (rl[mid] + mrows > r) hi = mid; else lo = mid + 1;
+        }
+        float acc = 0.f;
+        for (int j = lo; j < gpi && rl[j] <= r; ++j)
+            acc += mpart[((static_cast<int64_t>(b) * gpi + j) * 9 + l) * mrows * w +
+                         static_cast<int64_t>(r - rl[j]) * w + col];
+        dmap[i] = acc;
+    } else if (dbias && i < nmap + 3 * B) {
+        const int k = static_cast<int>(i - nmap), b = k / 3, c = k - 3 * (k / 3);
+        float acc = 0.f;
+        for (int j = 0; j < gpi; ++j) acc += dbpart[(static_cast<int64_t>(b) * gpi + j) * 3 + c];
+        dbias[k] = acc;
+    }
 }
 
 // Sum the per-workgroup dT partials (fixed order) and apply the chain rule of
@@ -602,6 +661,38 @@ size_t bwd_workspace_bytes(int B, int D) {
     return sizeof(float) * nlut * static_cast<size_t>(B) * bwd_groups_per_image(B);
 }
 
+// Segments per workgroup and the map rows its band can touch (the map-row accumulator's
+// height before the LDS check, which may only lower it to 0).
+static void bwd_band(int B, int H, int W, int h, int64_t& per, int& mrows) {
+    const int gpi = bwd_groups_per_image(B);
+    const int nseg = (W + kSeg - 1) / kSeg;
+    const int64_t tpi = static_cast<int64_t>(H) * nseg;
+    per = (tpi + gpi - 1) / gpi;
+    const int64_t band_rows = per / nseg + 2;
+    const int64_t mr = (H > 1) ? (band_rows * (h - 1)) / (H - 1) + 3 : 1;
+    mrows = static_cast<int>(std::min<int64_t>(h, mr));
+}
+
+// Deterministic-mode partials: first map rows (int), dbias partials, map-row accumulators.
+struct DetLayout {
+    size_t rowlo, dbpart, mpart, total;
+};
+static DetLayout det_layout(int B, int H, int W, int h, int w) {
+    int64_t per;
+    int mrows;
+    bwd_band(B, H, W, h, per, mrows);
+    const size_t nwg = static_cast<size_t>(B) * bwd_groups_per_image(B);
+    auto al = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
+    DetLayout L;
+    L.rowlo = 0;
+    L.dbpart = al(nwg * sizeof(int));
+    L.mpart = L.dbpart + al(nwg * 3 * sizeof(float));
+    L.total = L.mpart + al(nwg * 9 * static_cast<size_t>(mrows) * w * sizeof(float));
+    return L;
+}
+
+size_t bwd_det_bytes(int B, int H, int W, int h, int w) { return det_layout(B, H, W, h, w).total; }
+
 // LDS of the backward: T (float) and dT (int32), the map-row accumulator (int32), and per
 // wave the raw map rows, the blended map row (float) and its gradient (int32); the LUT
 // rebuild scratch and the block reductions reuse the staging area.
@@ -634,19 +725,14 @@ static svdlut_status launch_bwd_impl(const BwdLaunch& a, const LossArgs* L, hipS
         P.inv_n = static_cast<float>(1.0 / (3.0 * static_cast<double>(a.B) * a.H * a.W));
     }
     P.gpi = bwd_groups_per_image(a.B);
-    const int nseg = (a.W + kSeg - 1) / kSeg;
-    const int64_t tpi = static_cast<int64_t>(a.H) * nseg;
-    P.per = (tpi + P.gpi - 1) / P.gpi;
+    int mrows = 0;
+    bwd_band(a.B, a.H, a.W, a.h, P.per, mrows);
     P.ncol_max = map_cols_bound(a.W, a.w);
     P.fast_map = map_fast_ok(a.W, a.w) ? 1 : 0;
     P.want_dT = a.dU != nullptr;
     P.want_dmap = a.dmap != nullptr;
     P.want_dx = a.dx != nullptr;
     P.want_db = a.dbias != nullptr;
-    // map rows touched by one band of P.per segments
-    const int64_t band_rows = P.per / nseg + 2;
-    const int64_t mr = (a.H > 1) ? (band_rows * (a.h - 1)) / (a.H - 1) + 3 : 1;
-    int mrows = static_cast<int>(std::min<int64_t>(a.h, mr));
     int block = 0;
     // fine maps need narrow workgroups for their per-wave column staging
     const int blocks[4] = {512, 256, 128, 64};
@@ -662,11 +748,22 @@ static svdlut_status launch_bwd_impl(const BwdLaunch& a, const LossArgs* L, hipS
     if (block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply_bwd: map too wide for the LDS staging");
     P.mrows = P.want_dmap ? mrows : 0;
     const size_t lds = bwd_lds(a.D, block, P.ncol_max, P.mrows, a.w, a.R);
-
-    if (a.dmap) hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, a.dmap,
-                                   static_cast<int64_t>(a.B) * 9 * a.h * a.w);
-    if (a.dbias) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, a.dbias,
-                                    static_cast<int64_t>(a.B) * 3);
+    const bool det = a.det && (a.dmap || a.dbias);
+    if (det) {
+        if (a.dmap && P.mrows == 0)
+            return fail(SVDLUT_EUNSUPPORTED, "apply_bwd: deterministic mode needs the map-row accumulator, "
+                                             "which does not fit the LDS for this map");
+        const DetLayout L = det_layout(a.B, a.H, a.W, a.h, a.w);
+        char* base = static_cast<char*>(a.det);
+        P.rowlo = reinterpret_cast<int*>(base + L.rowlo);
+        P.dbpart = a.dbias ? reinterpret_cast<float*>(base + L.dbpart) : nullptr;
+        P.mpart = a.dmap ? reinterpret_cast<float*>(base + L.mpart) : nullptr;
+    } else {
+        if (a.dmap) hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, a.dmap,
+                                       static_cast<int64_t>(a.B) * 9 * a.h * a.w);
+        if (a.dbias) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, a.dbias,
+                                        static_cast<int64_t>(a.B) * 3);
+    }
     const int grid = a.B * P.gpi;
 #define SVDLUT_BWD_L(IO, MT, LS)                                                                \
     do {                                                                                        \
@@ -690,6 +787,13 @@ static svdlut_status launch_bwd_impl(const BwdLaunch& a, const LossArgs* L, hipS
 #undef SVDLUT_BWD_L
     svdlut_status stt = check_launch("apply_bwd");
     if (stt != SVDLUT_OK) return stt;
+    if (det) {
+        const int64_t n = (a.dmap ? static_cast<int64_t>(a.B) * 9 * a.h * a.w : 0) + (a.dbias ? 3 * a.B : 0);
+        hipLaunchKernelGGL(det_reduce_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                           P.rowlo, P.mpart, P.dbpart, a.dmap, a.dbias, a.B, P.gpi, P.mrows, a.h, a.w);
+        stt = check_launch("apply_bwd deterministic reduction");
+        if (stt != SVDLUT_OK) return stt;
+    }
     if (L) {
         hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(64), 0, st, L->lpart, grid, P.inv_n, L->loss);
         stt = check_launch("apply_loss_bwd");
@@ -751,6 +855,15 @@ svdlut_status svdlut_apply_loss_bwd(const void* x, const void* target, svdlut_dt
     a.x = x; a.dy = target; a.U = U; a.s = s; a.V = V; a.map = map;
     a.dx = dx; a.dU = dU; a.ds = ds; a.dV = dV; a.dmap = dmap; a.dbias = dbias;
     a.dT = static_cast<float*>(ws);
+    if ((dmap || dbias) && deterministic_mode()) {
+        const size_t base = (loss_bwd_ws_bytes(B, D) + 255) & ~static_cast<size_t>(255);
+        const size_t need = base + bwd_det_bytes(B, H, W, h, w);
+        if (ws_bytes < need)
+            return fail(SVDLUT_EINVAL, "apply_loss_bwd: deterministic mode needs a workspace of " +
+                                           std::to_string(need) + " bytes (the usual size plus "
+                                           "svdlut_deterministic_workspace_size())");
+        a.det = static_cast<char*>(ws) + base;
+    }
     a.B = B; a.H = H; a.W = W; a.h = h; a.w = w; a.D = D; a.R = R;
     a.io = io; a.map_dt = map_dt;
     LossArgs L{kind == SVDLUT_LOSS_L1 ? 1 : 2, bias,

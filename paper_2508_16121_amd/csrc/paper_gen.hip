@@ -204,16 +204,29 @@ __global__ void __launch_bounds__(kNormThreads) norm_bwd_stats_kernel(const floa
     if (t < C) part[static_cast<int64_t>(blockIdx.x) * C + c] = make_float2(r0[c], r1[c]);
 }
 
-// dz = dL/d(conv output before LeakyReLU) over this chunk; chunk 0 of each image adds the
-// image's scale and shift gradients.
+// Scale and shift gradients of one norm: per channel, the sums of da * xhat and of da over
+// the whole batch, from the chunk partials in chunk order.
+__global__ void norm_param_grad_kernel(const float2* __restrict__ part, int nparts, int C,
+                                       float* __restrict__ dgamma, float* __restrict__ dbeta) {
+    const int c = threadIdx.x;
+    if (c >= C) return;
+    float s0 = 0.f, s1 = 0.f;
+    for (int i = 0; i < nparts; ++i) {
+        const float2 v = part[static_cast<int64_t>(i) * C + c];
+        s0 += v.x;
+        s1 += v.y;
+    }
+    dbeta[c] = s0;
+    dgamma[c] = s1;
+}
+
+// dz = dL/d(conv output before LeakyReLU) over this chunk.
 __global__ void __launch_bounds__(kNormThreads) norm_bwd_apply_kernel(const float* __restrict__ h,
                                                                         const float* __restrict__ da,
                                                                         const float2* __restrict__ part,
                                                                         const float* __restrict__ mu,
                                                                         const float* __restrict__ rs,
                                                                         const float* __restrict__ gamma,
-                                                                        float* __restrict__ dgamma,
-                                                                        float* __restrict__ dbeta,
                                                                         float* __restrict__ dz, int HW, int C) {
     __shared__ float r0[kNormThreads], r1[kNormThreads];
     __shared__ float coef[2][64];
@@ -223,10 +236,6 @@ __global__ void __launch_bounds__(kNormThreads) norm_bwd_apply_kernel(const floa
     merge_partials(part, b, nch, C, r0, r1);
     if (t < C) {
         const float s0 = r0[t], s1 = r1[t];
-        if (ch == 0) {
-            __hip_atomic_fetch_add(dbeta + t, s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __hip_atomic_fetch_add(dgamma + t, s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         const float inv = 1.f / static_cast<float>(HW);
         coef[0][t] = gamma[t] * s0 * inv;
         coef[1][t] = gamma[t] * s1 * inv;
@@ -662,8 +671,10 @@ svdlut_status paper_generator_backward(const float* params, const uint8_t* mask,
         float2* bpart = reinterpret_cast<float2*>(k.part);
         hipLaunchKernelGGL(norm_bwd_stats_kernel, grid, dim3(kNormThreads), 0, st, k.h[i - 1], k.da[i - 1],
                            k.mu[i - 1], k.rs[i - 1], bpart, HW, C);
+        hipLaunchKernelGGL(norm_param_grad_kernel, dim3(1), dim3(64), 0, st, bpart, static_cast<int>(grid.x), C,
+                           G.ng[i - 1], G.nb[i - 1]);
         hipLaunchKernelGGL(norm_bwd_apply_kernel, grid, dim3(kNormThreads), 0, st, k.h[i - 1], k.da[i - 1], bpart,
-                           k.mu[i - 1], k.rs[i - 1], P.ng[i - 1], G.ng[i - 1], G.nb[i - 1], k.dz[i - 1], HW, C);
+                           k.mu[i - 1], k.rs[i - 1], P.ng[i - 1], k.dz[i - 1], HW, C);
     }
     return check_launch("paper_generator_bwd");
 }

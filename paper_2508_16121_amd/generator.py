@@ -13,7 +13,8 @@ import torch
 
 from . import _lib
 from ._lib import check
-from .ops import _DT, _need, _ptr, _stream, apply, apply_bwd, apply_loss_bwd, bwd_workspace, loss, loss_bwd_workspace
+from .ops import _DT, _need, _ptr, _stream, apply, apply_bwd, apply_loss_bwd, bwd_workspace, deterministic, loss, \
+    loss_bwd_workspace
 
 CONV_CH = (3, 16, 32, 64, 128, 128)
 HEAD_IN = 64
@@ -163,12 +164,13 @@ class Trainer:
 
     def step(self, x, target):
         U, s, V, m = self.gen.forward(x)
-        B = x.shape[0]
-        if B not in self._bws:
-            self._bws[B] = loss_bwd_workspace(B, self.gen.D, x.device)
+        B, _, H, W = x.shape
+        key = (B, H, W, deterministic())
+        if key not in self._bws:
+            self._bws[key] = loss_bwd_workspace(B, self.gen.D, x.device, (H, W, m.shape[2], m.shape[3]))
         # forward, MSE and backward of the transform in one fused pass
         r = apply_loss_bwd(x, target, U, s, V, m, kind="mse", need_dx=False, need_factors=True, need_map=True,
-                           ws=self._bws[B])
+                           ws=self._bws[key])
         self.gen.backward(r["dU"], r["ds"], r["dV"], r["dmap"])
         self.opt.step(self.gen.grads)
         return r["loss"]

@@ -119,14 +119,32 @@ def apply_grid(x, U, s, V, smap, grids, gw, gb, bias=None, out=None):
                                 B, H, W, h, w, D, R, _stream()), "svdlut_apply_grid")
     return out
 
-def bwd_workspace(B, D, device):
+def deterministic(on=None):
+    """The library's deterministic mode (svdlut_set_deterministic / svdlut_get_deterministic):
+    with no argument, whether it is on; otherwise switch it and return the new state."""
+    lib = _lib.load()
+    if on is not None:
+        lib.svdlut_set_deterministic(1 if on else 0)
+    return bool(lib.svdlut_get_deterministic())
+
+
+def _workspace(n, dims, device):
+    """n bytes of a backward workspace, plus (deterministic mode, dims = (B, H, W, h, w)) the
+    dmap/dbias partials after n rounded up to 256 bytes."""
+    if dims is not None and deterministic():
+        n = (n + 255) // 256 * 256 + _lib.load().svdlut_deterministic_workspace_size(*dims)
+    return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)
+
+
+def bwd_workspace(B, D, device, dims=None):
+    """Workspace of svdlut_apply_bwd; dims = (H, W, h, w) adds the deterministic-mode share."""
     n = _lib.load().svdlut_apply_bwd_workspace_size(B, D)
-    return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)
+    return _workspace(n, None if dims is None else (B, *dims), device)
 
 
-def grid_bwd_workspace(B, D, Ds, device):
+def grid_bwd_workspace(B, D, Ds, device, dims=None):
     n = _lib.load().svdlut_apply_grid_bwd_workspace_size(B, D, Ds)
-    return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)
+    return _workspace(n, None if dims is None else (B, *dims), device)
 
 
 def apply_bwd(x, dy, U, s, V, smap, need_dx=True, need_factors=True, need_map=True, need_bias=False,
@@ -148,8 +166,8 @@ def apply_bwd(x, dy, U, s, V, smap, need_dx=True, need_factors=True, need_map=Tr
     dV = torch.empty_like(V) if need_factors else None
     dmap = torch.empty(B, 9, h, w, device=dev, dtype=torch.float32) if need_map else None
     db = torch.empty(B, 3, device=dev, dtype=torch.float32) if need_bias else None
-    if need_factors and ws is None:
-        ws = bwd_workspace(B, D, dev)
+    if ws is None and (need_factors or ((need_map or need_bias) and deterministic())):
+        ws = bwd_workspace(B, D, dev, (H, W, h, w))
     lib = _lib.load()
     wsb = ws.numel() * ws.element_size() if ws is not None else 0
     check(lib.svdlut_apply_bwd(_ptr(x), _ptr(dy), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap),
@@ -161,9 +179,9 @@ def apply_bwd(x, dy, U, s, V, smap, need_dx=True, need_factors=True, need_map=Tr
     return out
 
 
-def loss_bwd_workspace(B, D, device):
+def loss_bwd_workspace(B, D, device, dims=None):
     n = _lib.load().svdlut_apply_loss_bwd_workspace_size(B, D)
-    return torch.empty(n // 4 + 64, dtype=torch.float32, device=device)
+    return _workspace(n, None if dims is None else (B, *dims), device)
 
 
 def apply_loss_bwd(x, target, U, s, V, smap, bias=None, kind="l1", need_dx=True, need_factors=True,
@@ -194,7 +212,7 @@ def apply_loss_bwd(x, target, U, s, V, smap, bias=None, kind="l1", need_dx=True,
     if need_bias:
         out["db"] = torch.empty(B, 3, **f32)
     if ws is None:
-        ws = loss_bwd_workspace(B, D, dev)
+        ws = loss_bwd_workspace(B, D, dev, (H, W, h, w))
     k = {"l1": _lib.LOSS_L1, "mse": _lib.LOSS_MSE}[kind]
     check(_lib.load().svdlut_apply_loss_bwd(
         _ptr(x), _ptr(target), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap), _DT[smap.dtype], _ptr(bias), k,
@@ -233,8 +251,8 @@ def apply_grid_bwd(x, dy, U, s, V, smap, grids, gw, need_dx=True, need_factors=T
     dgw = torch.empty_like(gw) if need_grids else None
     dgb = torch.empty(B, K, **f32) if need_grids else None
     lib = _lib.load()
-    if ws is None and (need_factors or need_grids):
-        ws = grid_bwd_workspace(B, D, Ds, dev)
+    if ws is None and (need_factors or need_grids or ((need_map or need_bias) and deterministic())):
+        ws = grid_bwd_workspace(B, D, Ds, dev, (H, W, h, w))
     wsb = ws.numel() * ws.element_size() if ws is not None else 0
     check(lib.svdlut_apply_grid_bwd(_ptr(x), _ptr(dy), _DT[x.dtype], _ptr(U), _ptr(s), _ptr(V), _ptr(smap),
                                     _DT[smap.dtype], _ptr(grids), _ptr(gw), K, Ds, _ptr(dx), _ptr(dU), _ptr(ds),

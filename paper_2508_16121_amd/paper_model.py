@@ -15,7 +15,7 @@ from . import _lib
 from ._lib import check
 from .generator import Adam
 from .ops import _DT, _need, _ptr, _stream, apply, apply_bwd, apply_grid, apply_grid_bwd, bwd_workspace, \
-    grid_bwd_workspace, loss
+    deterministic, grid_bwd_workspace, loss
 
 CH = (3, 8, 16, 32, 64, 64)
 HID = 8
@@ -217,15 +217,20 @@ class PaperTrainer:
         y = self.gen.transform(x, o)
         lval, dy = loss(y, target, "mse")
         g = self.gen
-        if B not in self._bws:
-            self._bws[B] = grid_bwd_workspace(B, g.D, g.Ds, x.device) if g.K else bwd_workspace(B, g.D, x.device)
+        H, W = x.shape[2], x.shape[3]
+        key = (B, H, W, deterministic())
+        if key not in self._bws:
+            dims = (H, W, 1, 1)         # the LUT-weight map is 9 x 1 x 1
+            self._bws[key] = (grid_bwd_workspace(B, g.D, g.Ds, x.device, dims) if g.K
+                              else bwd_workspace(B, g.D, x.device, dims))
+        ws = self._bws[key]
         if g.K:
             r = apply_grid_bwd(x, dy, o["U"], o["s"], o["V"], o["lut_w"], o["grids"], o["gw"], need_dx=False,
-                               need_bias=True, ws=self._bws[B])
+                               need_bias=True, ws=ws)
             up = {"U": r["dU"], "s": r["ds"], "V": r["dV"], "lut_w": r["dmap"], "lut_b": r["db"],
                   "grids": r["dgrids"], "gw": r["dgw"], "gb": r["dgb"]}
         else:
-            r = apply_bwd(x, dy, o["U"], o["s"], o["V"], o["lut_w"], need_dx=False, need_bias=True, ws=self._bws[B])
+            r = apply_bwd(x, dy, o["U"], o["s"], o["V"], o["lut_w"], need_dx=False, need_bias=True, ws=ws)
             up = {"U": r["dU"], "s": r["ds"], "V": r["dV"], "lut_w": r["dmap"], "lut_b": r["db"]}
         g.backward(up, m)
         self.opt.step(g.grads)

@@ -222,3 +222,53 @@ def test_noalloc_backward_validates_before_any_hip_call(lib):
     # the usual range checks
     assert lib.svdlut_apply_bwd_noalloc(*head, fake, fake, fake, None, None, 1, 4, 4, 1, 1, 41, 8, None) == 1
     assert lib.svdlut_apply_bwd_noalloc(*head, fake, fake, fake, None, None, 0, 4, 4, 1, 1, 33, 8, None) == 1
+
+
+def test_deterministic_mode_switch_and_workspace(lib):
+    """svdlut_set/get_deterministic, the extra workspace size, and the EINVAL a short
+    workspace gets in that mode (before any HIP call)."""
+    was = lib.svdlut_get_deterministic()
+    try:
+        lib.svdlut_set_deterministic(1)
+        assert lib.svdlut_get_deterministic() == 1
+        extra = lib.svdlut_deterministic_workspace_size(16, 512, 512, 64, 64)
+        # dbias and dmap partials of 16 x 16 workgroups, rounded to 256-byte blocks
+        assert extra >= 16 * 16 * (4 + 12 + 9 * 64 * 4)
+        assert lib.svdlut_deterministic_workspace_size(0, 512, 512, 64, 64) == 0
+        assert lib.svdlut_deterministic_workspace_size(1, 512, 512, 0, 64) == 0
+        fake = C.c_void_p(0x1000)
+        head = [fake, fake, 0, fake, fake, fake, fake, 0, None]
+        base = lib.svdlut_apply_bwd_workspace_size(2, 17)
+        need = (base + 255) // 256 * 256 + lib.svdlut_deterministic_workspace_size(2, 64, 64, 8, 8)
+        # dmap requested, no workspace: required in this mode even without dU
+        assert lib.svdlut_apply_bwd(*head, None, None, None, fake, None, 2, 64, 64, 8, 8, 17, 4, None, 0, None) == 1
+        assert "deterministic" in _err(lib)
+        # the usual size is one byte short of what the mode needs
+        assert lib.svdlut_apply_bwd(*head, fake, fake, fake, fake, fake, 2, 64, 64, 8, 8, 17, 4, fake,
+                                    need - 1, None) == 1
+        assert str(need) in _err(lib)
+        # the allocation-free variant: partials beyond its buffer
+        assert lib.svdlut_apply_bwd_noalloc(*head, None, None, None, fake, fake, 577, 4096, 4096, 4096, 4096,
+                                            33, 8, None) == 1
+        assert "deterministic" in _err(lib)
+        lib.svdlut_set_deterministic(0)
+        assert lib.svdlut_get_deterministic() == 0
+    finally:
+        lib.svdlut_set_deterministic(was)
+
+
+def test_deterministic_mode_from_environment():
+    """A fresh process reads SVDLUT_DETERMINISTIC: unset or "0" off, anything else on."""
+    import subprocess
+    import sys
+    code = ("from paper_2508_16121_amd import _lib; import sys; "
+            "sys.stdout.write(str(_lib.load().svdlut_get_deterministic()))")
+    for val, want in ((None, "0"), ("0", "0"), ("", "0"), ("1", "1"), ("yes", "1")):
+        env = dict(os.environ)
+        env.pop("SVDLUT_DETERMINISTIC", None)
+        if val is not None:
+            env["SVDLUT_DETERMINISTIC"] = val
+        r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, env=env, capture_output=True, text=True,
+                           timeout=120)
+        assert r.returncode == 0, r.stderr
+        assert r.stdout.strip() == want, (val, r.stdout)

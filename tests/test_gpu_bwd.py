@@ -413,3 +413,76 @@ def test_backward_heavy_tailed_inputs(svd, case):
         scale = np.abs(ref_n[k] if case != "map outliers" else ref[k]).max()
         say(f"  {k}: max-abs {err:.3e}, scale {scale:.3e}")
         assert err <= 1e-4 * scale, k
+
+
+@pytest.mark.parametrize("shape", [
+    (2, 256, 384, 33, 8, 16, 24),     # 128 workgroups per image, each map row shared by several
+    (3, 40, 70, 5, 3, 30, 40),        # per-pixel map columns, ragged
+    (1, 33, 300, 17, 4, 1, 1),        # a 1 x 1 map: every workgroup adds to the same entries
+])
+def test_deterministic_mode_bitwise(svd, shape):
+    """Deterministic mode: svdlut_apply_bwd, svdlut_apply_loss_bwd and svdlut_apply_grid_bwd
+    give bitwise the same outputs on repeated calls (dmap and dbias included, from
+    per-workgroup partials added in workgroup order); dmap and dbias agree with the default
+    mode's float atomics to 1e-6 of their largest value, the other outputs bitwise; all of them
+    match the oracle to 1e-4; a workspace without the mode's share is refused."""
+    B, H, W, D, R, h, w = shape
+    say(f"deterministic mode {shape}")
+    g = np.random.default_rng(sum(shape))
+    x = g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)
+    U, s, V = synth.factors(g, B, D, R)
+    m = synth.spatial_map(g, B, h, w)
+    G = g.uniform(-0.25, 0.25, (B, 3, H, W)).astype(np.float32)
+    tg = g.uniform(0, 1, (B, 3, H, W)).astype(np.float32)
+    args = (dev(x), dev(G), dev(U), dev(s), dev(V), dev(m))
+    was = svd.deterministic()
+    try:
+        svd.deterministic(False)
+        r0 = svd.apply_bwd(*args, need_bias=True)
+        f0 = svd.apply_loss_bwd(dev(x), dev(tg), *args[2:], kind="mse", need_bias=True)
+        svd.deterministic(True)
+        r1 = svd.apply_bwd(*args, need_bias=True)
+        r2 = svd.apply_bwd(*args, need_bias=True,
+                           ws=svd.bwd_workspace(B, D, "cuda", (H, W, h, w)))
+        f1 = svd.apply_loss_bwd(dev(x), dev(tg), *args[2:], kind="mse", need_bias=True)
+        f2 = svd.apply_loss_bwd(dev(x), dev(tg), *args[2:], kind="mse", need_bias=True)
+        with pytest.raises(svd.SvdlutError):
+            svd.apply_bwd(*args, need_bias=True, ws=svd.bwd_workspace(B, D, "cuda"))
+        torch.cuda.synchronize()
+    finally:
+        svd.deterministic(was)
+    for k in r1:
+        assert torch.equal(r1[k], r2[k]), k
+        if k in ("dmap", "db"):
+            close(host(r1[k]), host(r0[k]), 1e-6, k)
+        else:
+            assert torch.equal(r1[k], r0[k]), k
+    for k in f1:
+        assert torch.equal(f1[k], f2[k]), k
+    close(host(f1["dmap"]), host(f0["dmap"]), 1e-6, "fused dmap")
+    ref = ol.apply_bwd(x, U, s, V, m, G)
+    for k in ("dU", "ds", "dV", "dmap", "db"):
+        close(host(r1[k]), ref[k], 1e-4, k)
+
+
+def test_deterministic_mode_grid_backward_bitwise(svd):
+    """The bilateral-grid backward in deterministic mode: repeated calls bitwise equal."""
+    B, H, W, D, R, h, w, K, Ds = 2, 96, 160, 17, 4, 8, 12, 6, 17
+    say("deterministic mode, grid backward")
+    g = np.random.default_rng(61)
+    x = g.uniform(0, 1, (B, 3, H, W)).astype(np.float32)
+    U, s, V = synth.factors(g, B, D, R)
+    m = synth.spatial_map(g, B, h, w)
+    gr, gw, _ = synth.grids(g, B, K, Ds)
+    G = g.normal(0, 1, (B, 3, H, W)).astype(np.float32)
+    args = (dev(x), dev(G), dev(U), dev(s), dev(V), dev(m), dev(gr), dev(gw))
+    was = svd.deterministic()
+    try:
+        svd.deterministic(True)
+        a = svd.apply_grid_bwd(*args, need_bias=True)
+        b = svd.apply_grid_bwd(*args, need_bias=True)
+        torch.cuda.synchronize()
+    finally:
+        svd.deterministic(was)
+    for k in a:
+        assert torch.equal(a[k], b[k]), k

@@ -210,10 +210,19 @@ def test_training_gain_over_fixed_factors(svd, G, data):
 
 
 def test_checkpoint_resume(svd, G, data, tmp_path):
-    """N steps, save, reload into fresh objects, N more steps vs 2N uninterrupted.  Float
-    atomics in the gradient reductions make two uninterrupted runs differ at rounding level,
-    so the resumed run must be as close to the uninterrupted one as a second uninterrupted
-    run is, and far from a run that did not load the checkpoint."""
+    """N steps, save, reload into fresh objects, N more steps vs 2N uninterrupted, in
+    deterministic mode: every reduction of the training step has a fixed order, so two
+    uninterrupted runs and the resumed run end with bitwise the same parameters, and a run
+    that did not load the checkpoint ends far from them."""
+    was = svd.deterministic()
+    svd.deterministic(True)
+    try:
+        _checkpoint_resume(svd, G, data, tmp_path)
+    finally:
+        svd.deterministic(was)
+
+
+def _checkpoint_resume(svd, G, data, tmp_path):
     n = 20
     gen_a, _ = train_generator(svd, G, data, steps=2 * n, seed=7)
     gen_a2, _ = train_generator(svd, G, data, steps=2 * n, seed=7)
@@ -229,8 +238,9 @@ def test_checkpoint_resume(svd, G, data, tmp_path):
         idx = torch.from_numpy(g.integers(0, xtr.shape[0], BATCH)).cuda()
         if it >= n:
             tr_c.step(xtr.index_select(0, idx).contiguous(), ttr.index_select(0, idx).contiguous())
+    torch.cuda.synchronize()
     a, a2, b, c = host(gen_a.params), host(gen_a2.params), host(gen_b.params), host(gen_c.params)
     assert tr_c.opt.t == 2 * n
-    noise = np.abs(a - a2).mean()
-    assert np.abs(a - c).mean() <= 3 * noise + 1e-7
-    assert np.abs(a - b).mean() > 10 * (np.abs(a - c).mean() + 1e-9)
+    assert np.array_equal(a, a2), "two uninterrupted runs differ"
+    assert np.array_equal(a, c), f"resumed run differs: max {np.abs(a - c).max():.3e}"
+    assert np.abs(a - b).mean() > 1e-6

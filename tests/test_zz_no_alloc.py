@@ -60,6 +60,8 @@ def _run(lib, noalloc, x, G, U, s, V, m):
         status = lib.svdlut_apply_bwd_noalloc(*common, stream)
     else:
         n = lib.svdlut_apply_bwd_workspace_size(B, D)
+        if lib.svdlut_get_deterministic():
+            n = (n + 255) // 256 * 256 + lib.svdlut_deterministic_workspace_size(B, H, W, h, w)
         ws = torch.empty(n // 4 + 64, device="cuda", dtype=torch.float32)
         status = lib.svdlut_apply_bwd(*common, _p(ws), ws.numel() * 4, stream)
     assert status == 0, lib.svdlut_last_error().decode()
@@ -91,6 +93,25 @@ def test_noalloc_matches_workspace_entry_point_twice(lib):
         a = _run(lib, True, *case)
         b = _run(lib, False, *case)
         _same(a, b, ref, what)
+
+
+def test_noalloc_deterministic_mode_bitwise_twice(lib):
+    """In deterministic mode the library buffer also holds the dmap and dbias partials: both
+    entry points then agree bit for bit on every output, on two calls in a row."""
+    was = lib.svdlut_get_deterministic()
+    lib.svdlut_set_deterministic(1)
+    try:
+        for what, case in (("first call", _case(903, 3, 70, 530, 33, 8, 9, 67)),
+                           ("second call, smaller", _case(904, 1, 21, 100, 17, 4, 3, 13))):
+            print(f"noalloc deterministic {what}: shape {case[0].shape}", flush=True)
+            ref = ol.apply_bwd(*[case[i] for i in (0, 2, 3, 4, 5, 1)])
+            a = _run(lib, True, *case)
+            b = _run(lib, False, *case)
+            for k in a:
+                assert np.array_equal(a[k], b[k]), f"{what}: {k}"
+            _same(a, b, ref, what)
+    finally:
+        lib.svdlut_set_deterministic(was)
 
 
 def test_noalloc_rejects_batches_beyond_its_buffer(lib):
