@@ -51,6 +51,9 @@ def parse():
     ap.add_argument("--summarize-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="no GPU: summarise two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "`bench.py --rows none --copy-probe` into profiles/apply_4k_fp32_traffic.json")
+    ap.add_argument("--summarize-mfma", nargs=2, metavar=("TRACE_DIR", "PMC_DIR"),
+                    help="no GPU: MFMA utilisation of the generator GEMMs from a --kernel-trace run and a --pmc "
+                         "run of `bench.py --rows c5` into profiles/generator_mfma_counters.json")
     ap.add_argument("--command", default="", help="the profiler command recorded in a summary")
     return ap.parse_args()
 
@@ -75,13 +78,34 @@ KERNEL_SOURCES = ("paper_2508_16121_amd/csrc/lut_fwd.hip", "paper_2508_16121_amd
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_4k_fp32_traffic.json")
 
 
-def kernel_hash():
+def kernel_hash(sources=KERNEL_SOURCES):
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+GEN_SOURCES = ("paper_2508_16121_amd/csrc/gen_common.h", "paper_2508_16121_amd/csrc/gen.hip")
+MFMA_FILE = os.path.join(ROOT, "profiles", "generator_mfma_counters.json")
+GEMM_KERNEL = "mfma_gemm_kernel"
+# MFMA ops counters count in units of 512 flops (v_mfma_f32_16x16x32_bf16: 16384 flops = 32)
+MOPS_FLOPS = 512
+
+
+def mfma_counters():
+    """Counter-based MFMA figures of the generator's GEMM kernels from the committed summary
+    (or None when the generator sources changed since it was taken)."""
+    try:
+        with open(MFMA_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_hash") != kernel_hash(GEN_SOURCES):
+        return None
+    return {k: t[k] for k in ("gemm_tflops", "gemm_frac_of_bf16_peak", "mfma_busy_frac", "gemm_time_share")} | \
+        {"source": os.path.relpath(MFMA_FILE, ROOT)}
 
 
 TRACE_FILE = os.path.join(ROOT, "profiles", "apply_4k_fp32_kernel_trace.json")
@@ -182,6 +206,34 @@ def summarize_traffic(args):
            "bytes_read_per_launch": rd, "bytes_written_per_launch": wr, "bytes_per_launch": rd + wr,
            "algorithmic_bytes_per_launch": HEADLINE_BYTES, "commands": args.command.split(" ;; ")}
     with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
+
+
+def summarize_mfma(args):
+    """MFMA utilisation of the generator GEMMs from a --kernel-trace run and a --pmc run
+    (SQ_INSTS_VALU_MFMA_MOPS_BF16, SQ_VALU_MFMA_BUSY_CYCLES, SQ_BUSY_CU_CYCLES) of
+    `bench.py --rows c5`."""
+    trace_dir, pmc_dir = args.summarize_mfma
+    stats = _csvs(trace_dir, "kernel_stats.csv")
+    t_all = sum(float(r["TotalDurationNs"]) for r in stats)
+    g = [r for r in stats if GEMM_KERNEL in r["Name"]]
+    t_gemm = sum(float(r["TotalDurationNs"]) for r in g)
+    calls = sum(int(r["Calls"]) for r in g)
+    tot = {}
+    for r in _csvs(pmc_dir, "counter_collection.csv"):
+        if GEMM_KERNEL in r["Kernel_Name"]:
+            tot[r["Counter_Name"]] = tot.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    flops = tot["SQ_INSTS_VALU_MFMA_MOPS_BF16"] * MOPS_FLOPS
+    tflops = flops / (t_gemm * 1e-9) / 1e12
+    out = {"kernel": GEMM_KERNEL, "kernel_hash": kernel_hash(GEN_SOURCES), "kernel_hash_sources": list(GEN_SOURCES),
+           "dispatches": calls, "gemm_time_ns": t_gemm, "gemm_time_share": round(t_gemm / t_all, 4),
+           "counters": {k: v for k, v in sorted(tot.items())}, "mfma_flops": flops,
+           "gemm_tflops": round(tflops, 3), "gemm_frac_of_bf16_peak": round(tflops / BF16_PEAK_TFLOPS, 5),
+           "mfma_busy_frac": round(tot["SQ_VALU_MFMA_BUSY_CYCLES"] / tot["SQ_BUSY_CU_CYCLES"], 5),
+           "commands": args.command.split(" ;; ")}
+    with open(MFMA_FILE, "w") as f:
         json.dump(out, f, indent=1)
         f.write("\n")
     print(json.dumps(out))
@@ -571,7 +623,9 @@ def row_c5(svd, torch, synth, args):
             "infer_ms_per_batch8": round(ms_inf, 4), "infer_mpix_s": round(8 * 3840 * 2160 / (ms_inf * 1e-3) / 1e6, 1),
             "generator_fwd_ms_batch8": round(ms_gen, 4), "generator_mac_per_image": macs,
             "generator_tflops": round(tflops, 3), "mfma_frac_of_bf16_peak": round(tflops / BF16_PEAK_TFLOPS, 6),
-            "train_step_ms_batch16": round(ms_train, 4), "train_steps_s": round(1000.0 / ms_train, 1)}
+            "train_step_ms_batch16": round(ms_train, 4), "train_steps_s": round(1000.0 / ms_train, 1),
+            # the GEMM kernels under rocprofv3 counters (committed summary of this same row)
+            "mfma_counters": mfma_counters()}
 
 
 def row_p1(svd, torch, synth, args):
@@ -622,6 +676,8 @@ def main():
         return summarize_trace(args)
     if args.summarize_traffic:
         return summarize_traffic(args)
+    if args.summarize_mfma:
+        return summarize_mfma(args)
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)

@@ -44,9 +44,21 @@ typedef enum {
     SVDLUT_EDEVICE = 4        /* a HIP call or kernel launch failed */
 } svdlut_status;
 
-typedef enum { SVDLUT_F32 = 0, SVDLUT_F16 = 1 } svdlut_dtype;
+/* The enumerations take any int32 value across the ABI (the range markers make every value
+ * representable, so an unknown one is an EUNSUPPORTED or EINVAL argument, not undefined). */
+typedef enum {
+    SVDLUT_F32 = 0,
+    SVDLUT_F16 = 1,
+    SVDLUT_DTYPE_RANGE_MIN_ = -2147483647 - 1,
+    SVDLUT_DTYPE_RANGE_MAX_ = 2147483647
+} svdlut_dtype;
 
-typedef enum { SVDLUT_LOSS_L1 = 0, SVDLUT_LOSS_MSE = 1 } svdlut_loss_kind;
+typedef enum {
+    SVDLUT_LOSS_L1 = 0,
+    SVDLUT_LOSS_MSE = 1,
+    SVDLUT_LOSS_RANGE_MIN_ = -2147483647 - 1,
+    SVDLUT_LOSS_RANGE_MAX_ = 2147483647
+} svdlut_loss_kind;
 
 /* Message for the calling thread's most recent failed call ("" if none). */
 const char* svdlut_last_error(void);
@@ -326,6 +338,7 @@ svdlut_status svdlut_apply_loss_bwd(const void* x, const void* target, svdlut_dt
  *   [64][3][3][32], conv3.b, conv4.w [128][3][3][64], conv4.b, conv5.w [128][3][3][128],
  *   conv5.b, head.w [9][3][3][64], head.b [9], fc.w [9*(2DR+R)][128], fc.b
  *   (convolution weights are [Cout][ky][kx][Cin]).
+ * B (images per call) is in [1, 4096] for both generators; the size queries return 0 beyond.
  * ws: workspace of svdlut_generator_workspace_size(B, D, R) bytes holding the
  *   activations of the last forward; svdlut_generator_bwd reads them, so the two calls
  *   must share ws and the parameters must not change between them.

@@ -31,3 +31,40 @@ def make_pair(idx: int, H: int = 256, W: int = 256):
 def make_pairs(first: int, count: int, H: int = 256, W: int = 256):
     xs, ts = zip(*(make_pair(first + i, H, W) for i in range(count)))
     return np.stack(xs), np.stack(ts)
+
+
+def _fill_shared(args):
+    """Worker of make_pairs_parallel: pairs [lo, hi) into the shared arrays."""
+    from multiprocessing import shared_memory
+    name, count, H, W, first, lo, hi = args
+    shm = shared_memory.SharedMemory(name=name)
+    try:
+        arr = np.ndarray((2, count, 3, H, W), np.float32, buffer=shm.buf)
+        for i in range(lo, hi):
+            arr[0, i], arr[1, i] = make_pair(first + i, H, W)
+        del arr
+    finally:
+        shm.close()
+    return hi - lo
+
+
+def make_pairs_parallel(first: int, count: int, H: int = 256, W: int = 256, workers: int = 16):
+    """make_pairs over `workers` fresh processes (spawned, so a parent that holds a GPU context
+    is never forked) writing into shared memory; returns (inputs, targets) float32 arrays."""
+    import multiprocessing as mp
+    from multiprocessing import shared_memory
+    nbytes = 2 * count * 3 * H * W * 4
+    shm = shared_memory.SharedMemory(create=True, size=max(nbytes, 1))
+    try:
+        step = -(-count // max(1, workers * 4))
+        jobs = [(shm.name, count, H, W, first, lo, min(count, lo + step)) for lo in range(0, count, step)]
+        with mp.get_context("spawn").Pool(max(1, workers)) as pool:
+            done = sum(pool.map(_fill_shared, jobs))
+        assert done == count
+        arr = np.ndarray((2, count, 3, H, W), np.float32, buffer=shm.buf)
+        xs, ts = arr[0].copy(), arr[1].copy()
+        del arr
+    finally:
+        shm.close()
+        shm.unlink()
+    return xs, ts

@@ -1,7 +1,7 @@
 // Learned generator of the factors and the spatial map: bilinear downsample, five stride-2
 // 3x3 convolutions with ReLU, a 3x3 map head, global average pooling and a fully connected
 // factor head; forward and backward.  Convolutions (forward, input gradient and weight
-// gradient) are implicit GEMMs on bf16 matrix cores (v_mfma_f32_16x16x16_bf16, fp32
+// gradient) are implicit GEMMs on bf16 matrix cores (v_mfma_f32_16x16x32_bf16, fp32
 // accumulation); operands are gathered straight from NHWC activations into the MFMA
 // register layout.  Activations are stored as bf16; pooling, FC, biases, gradients of the
 // activations and all parameter gradients are fp32.
@@ -382,7 +382,7 @@ size_t svdlut_generator_param_count(int32_t D, int32_t R) {
 }
 
 size_t svdlut_generator_workspace_size(int32_t B, int32_t D, int32_t R) {
-    if (B < 1 || D < 2 || D > kMaxD || R < 1 || R > kMaxR) return 0;
+    if (B < 1 || B > kMaxGenBatch || D < 2 || D > kMaxD || R < 1 || R > kMaxR) return 0;
     return generator_ws_bytes(B, D, R);
 }
 
@@ -391,7 +391,7 @@ svdlut_status svdlut_generator_fwd(const float* params, const void* x, svdlut_dt
                                    void* ws, size_t ws_bytes, hipStream_t stream) {
     if (!params || !x || !U || !s || !V || !map || !ws) return fail(SVDLUT_EINVAL, "generator_fwd: null pointer");
     if (io != SVDLUT_F32 && io != SVDLUT_F16) return fail(SVDLUT_EUNSUPPORTED, "generator_fwd: dtype");
-    if (B < 1 || H < 1 || W < 1 || H > kMaxDim || W > kMaxDim)
+    if (B < 1 || B > kMaxGenBatch || H < 1 || W < 1 || H > kMaxDim || W > kMaxDim)
         return fail(SVDLUT_EINVAL, "generator_fwd: B, H, W out of range");
     if (D < 2 || D > kMaxD || R < 1 || R > kMaxR) return fail(SVDLUT_EINVAL, "generator_fwd: D or R out of range");
     if (ws_bytes < generator_ws_bytes(B, D, R))
@@ -404,7 +404,7 @@ svdlut_status svdlut_generator_bwd(const float* params, const float* dU, const f
                                    size_t ws_bytes, hipStream_t stream) {
     if (!params || !dU || !ds || !dV || !dmap || !grads || !ws)
         return fail(SVDLUT_EINVAL, "generator_bwd: null pointer");
-    if (B < 1) return fail(SVDLUT_EINVAL, "generator_bwd: B must be >= 1");
+    if (B < 1 || B > kMaxGenBatch) return fail(SVDLUT_EINVAL, "generator_bwd: B must be in [1, 4096]");
     if (D < 2 || D > kMaxD || R < 1 || R > kMaxR) return fail(SVDLUT_EINVAL, "generator_bwd: D or R out of range");
     if (ws_bytes < generator_ws_bytes(B, D, R))
         return fail(SVDLUT_EINVAL, "generator_bwd: workspace smaller than svdlut_generator_workspace_size()");

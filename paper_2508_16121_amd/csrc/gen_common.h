@@ -232,10 +232,19 @@ struct EpiStore {        // plain fp32 store (or accumulate) of an NHWC gradient
 // ---------------------------------------------------------------- the MFMA GEMM
 // C[M][N] = sum_k A[m][k] B[k][n].  Workgroup = 4 waves; wave w owns rows
 // blockIdx.x*64 + 16w .. +15 and columns blockIdx.y*16*NT .. +16*NT-1 (NT 16x16 tiles),
-// over the k range [blockIdx.z*kchunk, +kchunk).  Per 16-wide k step each lane loads its
-// four A values (row lane%16, k lane/16*4..+3) and, per tile, four B values (column
-// lane%16, same k) and issues one v_mfma_f32_16x16x16_bf16; accumulator element i of lane
-// l is C[4*(l/16)+i][l%16].
+// over the k range [blockIdx.z*kchunk, +kchunk).  Per 32-wide k step each lane loads its
+// eight A values (row lane%16, k lane/16*8..+7) and, per tile, eight B values (column
+// lane%16, same k) and issues one v_mfma_f32_16x16x32_bf16 (gfx950); accumulator element i
+// of lane l is C[4*(l/16)+i][l%16].
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef short s16x8 __attribute__((ext_vector_type(8)));
+constexpr int kGemmK = 32;   // k per MFMA step
+
+__device__ __forceinline__ bf16x8 cat8(bf16x4 lo, bf16x4 hi) {
+    const s16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_bit_cast(bf16x8, v);
+}
+
 template <int NT, class AL, class BL, class EP>
 __global__ void __launch_bounds__(256) mfma_gemm_kernel(AL al, BL bl, EP ep, int K, int kchunk) {
     const int lane = threadIdx.x & 63;
@@ -251,24 +260,26 @@ __global__ void __launch_bounds__(256) mfma_gemm_kernel(AL al, BL bl, EP ep, int
     typename BL::Col bc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bc[t] = bl.col(n0 + 16 * t + (lane & 15));
-    const int kl = 4 * (lane >> 4);
-    // operands of step k + 16 are gathered while the matrix cores work on step k
-    bf16x4 a = al.load(ar, kb + kl);
-    bf16x4 b[NT];
+    const int kl = 8 * (lane >> 4);
+    // operands of step k + 32 are gathered while the matrix cores work on step k
+    bf16x8 a = cat8(al.load(ar, kb + kl), al.load(ar, kb + kl + 4));
+    bf16x8 b[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) b[t] = bl.load(bc[t], kb + kl);
-    for (int k = kb; k < ke; k += 16) {
-        bf16x4 an = {0, 0, 0, 0};
-        bf16x4 bn[NT];
+    for (int t = 0; t < NT; ++t) b[t] = cat8(bl.load(bc[t], kb + kl), bl.load(bc[t], kb + kl + 4));
+    for (int k = kb; k < ke; k += kGemmK) {
+        const bf16x4 z = {0, 0, 0, 0};
+        bf16x8 an = cat8(z, z);
+        bf16x8 bn[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) bn[t] = bf16x4{0, 0, 0, 0};
-        if (k + 16 < ke) {
-            an = al.load(ar, k + 16 + kl);
+        for (int t = 0; t < NT; ++t) bn[t] = cat8(z, z);
+        if (k + kGemmK < ke) {
+            an = cat8(al.load(ar, k + kGemmK + kl), al.load(ar, k + kGemmK + kl + 4));
 #pragma unroll
-            for (int t = 0; t < NT; ++t) bn[t] = bl.load(bc[t], k + 16 + kl);
+            for (int t = 0; t < NT; ++t)
+                bn[t] = cat8(bl.load(bc[t], k + kGemmK + kl), bl.load(bc[t], k + kGemmK + kl + 4));
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[t], 0, 0, 0);
         a = an;
 #pragma unroll
         for (int t = 0; t < NT; ++t) b[t] = bn[t];
@@ -279,20 +290,21 @@ __global__ void __launch_bounds__(256) mfma_gemm_kernel(AL al, BL bl, EP ep, int
         for (int i = 0; i < 4; ++i) ep(m0 + 4 * (lane >> 4) + i, n0 + 16 * t + (lane & 15), acc[t][i]);
 }
 
-// k range per workgroup and number of k slices for a requested split of a K-long reduction
+// k range per workgroup (a multiple of the MFMA step) and number of k slices for a requested
+// split of a K-long reduction
 inline int gemm_kchunk(int K, int splitk) {
-    const int Kp = (K + 15) / 16 * 16;
-    return ((Kp + splitk - 1) / splitk + 15) / 16 * 16;
+    const int Kp = (K + kGemmK - 1) / kGemmK * kGemmK;
+    return ((Kp + splitk - 1) / splitk + kGemmK - 1) / kGemmK * kGemmK;
 }
 inline int gemm_slices(int K, int splitk) {
-    const int Kp = (K + 15) / 16 * 16;
+    const int Kp = (K + kGemmK - 1) / kGemmK * kGemmK;
     const int kc = gemm_kchunk(K, splitk);
     return (Kp + kc - 1) / kc;
 }
 
 template <int NT, class AL, class BL, class EP>
 void gemm(AL al, BL bl, EP ep, int M, int N, int K, int splitk, hipStream_t st) {
-    const int Kp = (K + 15) / 16 * 16;
+    const int Kp = (K + kGemmK - 1) / kGemmK * kGemmK;
     const int kchunk = gemm_kchunk(K, splitk);
     const int gz = gemm_slices(K, splitk);
     dim3 grid((M + 63) / 64, (N + 16 * NT - 1) / (16 * NT), gz);
@@ -412,7 +424,7 @@ void gemm_nt(int ncols, AL al, BL bl, EP ep, int M, int K, int splitk, hipStream
 // the activation.  Returns the requested split (1 = no split) for an M x N x K product with
 // 16-column tiles.
 inline int fwd_splits(int M, int N, int K) {
-    const int ksteps = (K + 15) / 16;
+    const int ksteps = (K + kGemmK - 1) / kGemmK;
     const int wgs = ((M + 63) / 64) * ((N + 15) / 16);
     if (wgs >= 128) return 1;
     return std::max(1, std::min(ksteps / 2, (256 + wgs - 1) / wgs));
@@ -434,7 +446,7 @@ size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 inline int wgrad_splits(const ConvGeo& g) {
     const int Mo = g.N * g.Ho * g.Wo;
     const int wgs = ((g.Co + 63) / 64) * ((9 * g.Cs + 63) / 64);
-    const int ksteps = (Mo + 15) / 16;
+    const int ksteps = (Mo + kGemmK - 1) / kGemmK;
     return std::max(1, std::min(ksteps / 4, (2048 + wgs - 1) / wgs));
 }
 

@@ -14,6 +14,7 @@ namespace svdlut {
 constexpr int kMaxD = 40;
 constexpr int kMaxR = 64;
 constexpr int kMaxDim = 65535;
+constexpr int kMaxGenBatch = 4096;   // images per generator call (keeps its int sizes in range)
 constexpr int kWave = 64;
 constexpr int kPxPerLane = 4;                      // pixels per lane per row segment
 constexpr int kSeg = kWave * kPxPerLane;           // pixels per row segment (one wave)

@@ -700,7 +700,7 @@ size_t svdlut_paper_generator_param_count(int32_t D, int32_t R, int32_t K, int32
 }
 
 size_t svdlut_paper_generator_workspace_size(int32_t B, int32_t D, int32_t R, int32_t K, int32_t Ds) {
-    if (B < 1 || !pgen_dims_ok(D, R, K, Ds)) return 0;
+    if (B < 1 || B > kMaxGenBatch || !pgen_dims_ok(D, R, K, Ds)) return 0;
     return paper_generator_ws_bytes(B, D, R, K, Ds);
 }
 
@@ -712,7 +712,7 @@ svdlut_status svdlut_paper_generator_fwd(const float* params, const void* x, svd
     if (!params || !x || !U || !s || !V || !lut_w || !lut_b || !ws)
         return fail(SVDLUT_EINVAL, "paper_generator_fwd: null pointer");
     if (io != SVDLUT_F32 && io != SVDLUT_F16) return fail(SVDLUT_EUNSUPPORTED, "paper_generator_fwd: dtype");
-    if (B < 1 || H < 1 || W < 1 || H > kMaxDim || W > kMaxDim)
+    if (B < 1 || B > kMaxGenBatch || H < 1 || W < 1 || H > kMaxDim || W > kMaxDim)
         return fail(SVDLUT_EINVAL, "paper_generator_fwd: B, H, W out of range");
     if (!pgen_dims_ok(D, R, K, Ds)) return fail(SVDLUT_EINVAL, "paper_generator_fwd: D, R, K or Ds out of range");
     if (K > 0 && (!grids || !gw || !gb)) return fail(SVDLUT_EINVAL, "paper_generator_fwd: null grid output");
@@ -728,7 +728,7 @@ svdlut_status svdlut_paper_generator_bwd(const float* params, const uint8_t* kee
                                          int32_t B, int32_t D, int32_t R, int32_t K, int32_t Ds, void* ws,
                                          size_t ws_bytes, hipStream_t stream) {
     if (!params || !grads || !ws) return fail(SVDLUT_EINVAL, "paper_generator_bwd: null pointer");
-    if (B < 1) return fail(SVDLUT_EINVAL, "paper_generator_bwd: B must be >= 1");
+    if (B < 1 || B > kMaxGenBatch) return fail(SVDLUT_EINVAL, "paper_generator_bwd: B must be in [1, 4096]");
     if (!pgen_dims_ok(D, R, K, Ds)) return fail(SVDLUT_EINVAL, "paper_generator_bwd: D, R, K or Ds out of range");
     if (ws_bytes < paper_generator_ws_bytes(B, D, R, K, Ds))
         return fail(SVDLUT_EINVAL, "paper_generator_bwd: workspace smaller than svdlut_paper_generator_workspace_size()");

@@ -17,7 +17,7 @@ def pytest_report_header(config):
 
 
 # ------------------------------------------------------------------ training pairs
-N_TRAIN, N_HELD = 1024, 128
+N_TRAIN, N_HELD = 10_000, 128
 HELD0 = 100_000
 
 
@@ -35,14 +35,15 @@ def make_pairs(first, count):
 
 @pytest.fixture(scope="session")
 def pair_data():
-    """Training pairs 0..N_TRAIN-1 and held-out pairs from HELD0, on the GPU (shared by the
-    training tests of both generators)."""
+    """Training pairs 0..N_TRAIN-1 (10k, drawn over 16 worker processes) and held-out pairs
+    from HELD0, on the GPU (shared by the training tests of both generators)."""
     import time
 
     import torch
+    from oracle import pairs as op
     print("generating training pairs", flush=True)
     t = time.time()
-    xtr, ttr = make_pairs(0, N_TRAIN)
+    xtr, ttr = op.make_pairs_parallel(0, N_TRAIN, workers=16)
     xte, tte = make_pairs(HELD0, N_HELD)
     print(f"pairs ready in {time.time() - t:.1f}s", flush=True)
     cuda = lambda a: torch.from_numpy(a).cuda()

@@ -150,3 +150,90 @@ def test_plan_full_uneven_batch_sampled(svd):
     torch.cuda.synchronize()
     assert torch.equal(y, y_loop)
     oracle_check(packed, x, m, y, 2e-3, npx=300)
+
+
+_CHILD = r'''
+import json, sys
+import numpy as np, torch
+import synth
+import paper_2508_16121_amd as svd
+out, autotune = sys.argv[1], sys.argv[2] == "1"
+bases = ((48, 64), (108, 192), (216, 384))
+images = [synth.uneven_image(i, 960, 33, 8, bases) for i in range(5)]
+xf, mf, U, s, V, descs = synth.pack_uneven(images)
+x = torch.from_numpy(xf).cuda().half(); m = torch.from_numpy(mf).cuda().half()
+Ud, sd, Vd = (torch.from_numpy(a).cuda() for a in (U, s, V))
+plan = svd.Plan(descs, 33, 8, torch.float16, torch.float16)
+info0 = plan.info()
+if autotune:
+    plan.autotune(x, torch.zeros_like(x), Ud, sd, Vd, m)
+y = torch.zeros_like(x); plan.launch(x, y, Ud, sd, Vd, m)
+y2 = torch.zeros_like(x); plan.launch_direct(x, y2, Ud, sd, Vd, m)
+torch.cuda.synchronize()
+np.save(out + ".npy", y.cpu().numpy())
+json.dump({"before": info0, "after": plan.info(), "direct_equal": bool(torch.equal(y, y2))}, open(out + ".json", "w"))
+print("child done", flush=True)
+'''
+
+
+def _child(tmp_path, name, env_extra, autotune=False):
+    """Run one plan in a fresh process (the library reads SVDLUT_TUNE_CACHE and
+    SVDLUT_NO_GRAPH at first use) and return its info and output."""
+    import json
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ)
+    for k in ("SVDLUT_TUNE_CACHE", "SVDLUT_NO_GRAPH"):
+        env.pop(k, None)
+    env.update(env_extra)
+    out = str(tmp_path / name)
+    say(f"plan child {name}: {env_extra} autotune={autotune}")
+    r = subprocess.run([sys.executable, "-c", _CHILD, out, "1" if autotune else "0"], cwd=root, env=env,
+                       capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout[-3000:] + r.stderr[-3000:]
+    return json.load(open(out + ".json")), np.load(out + ".npy")
+
+
+def test_plan_fallbacks_and_tuning_cache(tmp_path):
+    """The plan's fallbacks, each in a fresh process: SVDLUT_NO_GRAPH gives plain launches
+    (graph = 0) with the same output bit for bit; a missing cache file leaves the default
+    shape and autotune writes a valid one; a later process takes its shape from that file
+    without tuning; a corrupt file, or an entry with values out of range, is ignored (the
+    default shape, the same output) and autotune replaces it with valid JSON.  The output is
+    the same bit for bit in every case: no pixel's arithmetic depends on the launch shape."""
+    import json
+    base, y_ref = _child(tmp_path, "graph", {})
+    assert base["before"]["graph"] == 1 or base["after"]["graph"] == 1
+    assert base["direct_equal"]
+    # no graph
+    nog, y = _child(tmp_path, "nograph", {"SVDLUT_NO_GRAPH": "1"})
+    assert nog["after"]["graph"] == 0 and nog["direct_equal"]
+    assert np.array_equal(y, y_ref)
+    # missing cache file: default shape, autotune creates the file
+    cache = tmp_path / "cache.json"
+    miss, y = _child(tmp_path, "missing", {"SVDLUT_TUNE_CACHE": str(cache)}, autotune=True)
+    assert miss["before"]["tuned"] == 0 and miss["after"]["tuned"] == 1
+    assert miss["before"]["block"] == base["before"]["block"]
+    entries = json.load(open(cache))
+    assert len(entries) == 1
+    key, (blk, bpc) = next(iter(entries.items()))
+    assert blk in (64, 128, 256, 512, 1024) and 1 <= bpc <= 32
+    # every pixel's arithmetic is independent of the launch shape: same output bit for bit
+    np.testing.assert_array_equal(y, y_ref)
+    # the cached shape is used by the next process without tuning
+    hit, y = _child(tmp_path, "hit", {"SVDLUT_TUNE_CACHE": str(cache)})
+    assert hit["before"]["tuned"] == 1 and hit["before"]["block"] == blk
+    assert hit["direct_equal"]
+    # corrupt files and out-of-range values are ignored
+    for name, text in (("garbage", "\x00\xffnot json{{{["), ("truncated", '{"' + key + '": [51'),
+                       ("range", json.dumps({key: [999, 2]})), ("types", json.dumps({key: ["512", "x"]}))):
+        cache.write_bytes(text.encode("latin-1"))
+        bad, y = _child(tmp_path, name, {"SVDLUT_TUNE_CACHE": str(cache)}, autotune=(name == "garbage"))
+        assert bad["before"]["tuned"] == 0, name
+        assert bad["before"]["block"] == base["before"]["block"], name
+        if name == "garbage":
+            fixed = json.load(open(cache))          # rewritten as valid JSON
+            assert list(fixed) == [key], fixed
+        np.testing.assert_array_equal(y, y_ref)
