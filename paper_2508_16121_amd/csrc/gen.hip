@@ -1,7 +1,7 @@
 // Learned generator of the factors and the spatial map: bilinear downsample, five stride-2
 // 3x3 convolutions with ReLU, a 3x3 map head, global average pooling and a fully connected
 // factor head; forward and backward.  Convolutions (forward, input gradient and weight
-// gradient) are implicit GEMMs on bf16 matrix cores (v_mfma_f32_16x16x32_bf16, fp32
+// gradient) are implicit GEMMs on bf16 matrix cores (v_mfma_f32_16x16x16_bf16, fp32
 // accumulation); operands are gathered straight from NHWC activations into the MFMA
 // register layout.  Activations are stored as bf16; pooling, FC, biases, gradients of the
 // activations and all parameter gradients are fp32.

@@ -232,19 +232,10 @@ struct EpiStore {        // plain fp32 store (or accumulate) of an NHWC gradient
 // ---------------------------------------------------------------- the MFMA GEMM
 // C[M][N] = sum_k A[m][k] B[k][n].  Workgroup = 4 waves; wave w owns rows
 // blockIdx.x*64 + 16w .. +15 and columns blockIdx.y*16*NT .. +16*NT-1 (NT 16x16 tiles),
-// over the k range [blockIdx.z*kchunk, +kchunk).  Per 32-wide k step each lane loads its
-// eight A values (row lane%16, k lane/16*8..+7) and, per tile, eight B values (column
-// lane%16, same k) and issues one v_mfma_f32_16x16x32_bf16 (gfx950); accumulator element i
-// of lane l is C[4*(l/16)+i][l%16].
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef short s16x8 __attribute__((ext_vector_type(8)));
-constexpr int kGemmK = 32;   // k per MFMA step
-
-__device__ __forceinline__ bf16x8 cat8(bf16x4 lo, bf16x4 hi) {
-    const s16x8 v = __builtin_shufflevector(lo, hi, 0, 1, 2, 3, 4, 5, 6, 7);
-    return __builtin_bit_cast(bf16x8, v);
-}
-
+// over the k range [blockIdx.z*kchunk, +kchunk).  Per 16-wide k step each lane loads its
+// four A values (row lane%16, k lane/16*4..+3) and, per tile, four B values (column
+// lane%16, same k) and issues one v_mfma_f32_16x16x16_bf16; accumulator element i of lane
+// l is C[4*(l/16)+i][l%16].
 template <int NT, class AL, class BL, class EP>
 __global__ void __launch_bounds__(256) mfma_gemm_kernel(AL al, BL bl, EP ep, int K, int kchunk) {
     const int lane = threadIdx.x & 63;
@@ -260,26 +251,24 @@ __global__ void __launch_bounds__(256) mfma_gemm_kernel(AL al, BL bl, EP ep, int
     typename BL::Col bc[NT];
 #pragma unroll
     for (int t = 0; t < NT; ++t) bc[t] = bl.col(n0 + 16 * t + (lane & 15));
-    const int kl = 8 * (lane >> 4);
-    // operands of step k + 32 are gathered while the matrix cores work on step k
-    bf16x8 a = cat8(al.load(ar, kb + kl), al.load(ar, kb + kl + 4));
-    bf16x8 b[NT];
+    const int kl = 4 * (lane >> 4);
+    // operands of step k + 16 are gathered while the matrix cores work on step k
+    bf16x4 a = al.load(ar, kb + kl);
+    bf16x4 b[NT];
 #pragma unroll
-    for (int t = 0; t < NT; ++t) b[t] = cat8(bl.load(bc[t], kb + kl), bl.load(bc[t], kb + kl + 4));
-    for (int k = kb; k < ke; k += kGemmK) {
-        const bf16x4 z = {0, 0, 0, 0};
-        bf16x8 an = cat8(z, z);
-        bf16x8 bn[NT];
+    for (int t = 0; t < NT; ++t) b[t] = bl.load(bc[t], kb + kl);
+    for (int k = kb; k < ke; k += 16) {
+        bf16x4 an = {0, 0, 0, 0};
+        bf16x4 bn[NT];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) bn[t] = cat8(z, z);
-        if (k + kGemmK < ke) {
-            an = cat8(al.load(ar, k + kGemmK + kl), al.load(ar, k + kGemmK + kl + 4));
+        for (int t = 0; t < NT; ++t) bn[t] = bf16x4{0, 0, 0, 0};
+        if (k + 16 < ke) {
+            an = al.load(ar, k + 16 + kl);
 #pragma unroll
-            for (int t = 0; t < NT; ++t)
-                bn[t] = cat8(bl.load(bc[t], k + kGemmK + kl), bl.load(bc[t], k + kGemmK + kl + 4));
+            for (int t = 0; t < NT; ++t) bn[t] = bl.load(bc[t], k + 16 + kl);
         }
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b[t], acc[t], 0, 0, 0);
+        for (int t = 0; t < NT; ++t) acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b[t], acc[t], 0, 0, 0);
         a = an;
 #pragma unroll
         for (int t = 0; t < NT; ++t) b[t] = bn[t];
@@ -290,21 +279,20 @@ __global__ void __launch_bounds__(256) mfma_gemm_kernel(AL al, BL bl, EP ep, int
         for (int i = 0; i < 4; ++i) ep(m0 + 4 * (lane >> 4) + i, n0 + 16 * t + (lane & 15), acc[t][i]);
 }
 
-// k range per workgroup (a multiple of the MFMA step) and number of k slices for a requested
-// split of a K-long reduction
+// k range per workgroup and number of k slices for a requested split of a K-long reduction
 inline int gemm_kchunk(int K, int splitk) {
-    const int Kp = (K + kGemmK - 1) / kGemmK * kGemmK;
-    return ((Kp + splitk - 1) / splitk + kGemmK - 1) / kGemmK * kGemmK;
+    const int Kp = (K + 15) / 16 * 16;
+    return ((Kp + splitk - 1) / splitk + 15) / 16 * 16;
 }
 inline int gemm_slices(int K, int splitk) {
-    const int Kp = (K + kGemmK - 1) / kGemmK * kGemmK;
+    const int Kp = (K + 15) / 16 * 16;
     const int kc = gemm_kchunk(K, splitk);
     return (Kp + kc - 1) / kc;
 }
 
 template <int NT, class AL, class BL, class EP>
 void gemm(AL al, BL bl, EP ep, int M, int N, int K, int splitk, hipStream_t st) {
-    const int Kp = (K + kGemmK - 1) / kGemmK * kGemmK;
+    const int Kp = (K + 15) / 16 * 16;
     const int kchunk = gemm_kchunk(K, splitk);
     const int gz = gemm_slices(K, splitk);
     dim3 grid((M + 63) / 64, (N + 16 * NT - 1) / (16 * NT), gz);
@@ -354,7 +342,7 @@ __global__ void downsample_kernel(const IO* __restrict__ x, uint16_t* __restrict
 // each); workgroup g takes chunks g, g + G, ... of nl * 16 pixels, adds its lanes in LDS and
 // stores one partial per channel; bias_sum_kernel adds the G partials in workgroup order.
 constexpr int kBiasPx = 16;
-constexpr int kBiasGroups = 256;
+constexpr int kBiasGroups = 1024;
 
 inline int bias_lanes(int Co) { return std::max(1, 256 / Co); }
 
@@ -377,12 +365,24 @@ __global__ void __launch_bounds__(256) bias_grad_kernel(DZ dz, float* __restrict
     }
 }
 
-__global__ void bias_sum_kernel(const float* __restrict__ part, int groups, int Co, float* __restrict__ db) {
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= Co) return;
+// db[c] = sum over g of part[g][c] (Co <= 256, one workgroup of 256 threads): thread (c, l)
+// adds rows l, l + L, ... in order (L = 256 / Co lanes per channel, loads issued eight at a
+// time), then the L lane sums of each channel are added in lane order.
+__global__ void __launch_bounds__(256) bias_sum_kernel(const float* __restrict__ part, int groups, int Co,
+                                                       float* __restrict__ db) {
+    __shared__ float red[256];
+    const int t = threadIdx.x, L = max(1, 256 / Co), c = t % Co, l = t / Co;
     float s = 0.f;
-    for (int g = 0; g < groups; ++g) s += part[static_cast<int64_t>(g) * Co + t];
-    db[t] = s;
+    if (l < L)
+#pragma unroll 8
+        for (int g = l; g < groups; g += L) s += part[static_cast<int64_t>(g) * Co + c];
+    red[t] = s;
+    __syncthreads();
+    if (t < Co) {
+        float v = 0.f;
+        for (int i = 0; i < L; ++i) v += red[i * Co + t];
+        db[t] = v;
+    }
 }
 
 // dW[co][tap][ci] = sum over the split-K slices of part[z][co][tap * Cs + ci]: one wave per
@@ -424,7 +424,7 @@ void gemm_nt(int ncols, AL al, BL bl, EP ep, int M, int K, int splitk, hipStream
 // the activation.  Returns the requested split (1 = no split) for an M x N x K product with
 // 16-column tiles.
 inline int fwd_splits(int M, int N, int K) {
-    const int ksteps = (K + kGemmK - 1) / kGemmK;
+    const int ksteps = (K + 15) / 16;
     const int wgs = ((M + 63) / 64) * ((N + 15) / 16);
     if (wgs >= 128) return 1;
     return std::max(1, std::min(ksteps / 2, (256 + wgs - 1) / wgs));
@@ -446,7 +446,7 @@ size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 inline int wgrad_splits(const ConvGeo& g) {
     const int Mo = g.N * g.Ho * g.Wo;
     const int wgs = ((g.Co + 63) / 64) * ((9 * g.Cs + 63) / 64);
-    const int ksteps = (Mo + kGemmK - 1) / kGemmK;
+    const int ksteps = (Mo + 15) / 16;
     return std::max(1, std::min(ksteps / 4, (2048 + wgs - 1) / wgs));
 }
 
@@ -472,7 +472,7 @@ void conv_backward(const ConvGeo& g, DZ dz, const uint16_t* in, const float* w, 
         1, std::min<size_t>({static_cast<size_t>((Mo + px_per_wg - 1) / px_per_wg), static_cast<size_t>(kBiasGroups),
                              wgrad_part_floats(g) / g.Co})));
     hipLaunchKernelGGL(bias_grad_kernel<DZ>, dim3(groups), dim3(256), 0, st, dz, wpart, Mo, g.Co);
-    hipLaunchKernelGGL(bias_sum_kernel, dim3((g.Co + 63) / 64), dim3(64), 0, st, wpart, groups, g.Co, db);
+    hipLaunchKernelGGL(bias_sum_kernel, dim3(1), dim3(256), 0, st, wpart, groups, g.Co, db);
     if (da_in) {
         const int Mi = g.N * g.Hi * g.Wi;
         gemm_nt(g.Ci, DgradA<DZ>{dz, g}, DgradB{w, g}, EpiStore{da_in, Mi, g.Cs, accumulate_da}, Mi,

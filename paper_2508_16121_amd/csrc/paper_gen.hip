@@ -205,19 +205,33 @@ __global__ void __launch_bounds__(kNormThreads) norm_bwd_stats_kernel(const floa
 }
 
 // Scale and shift gradients of one norm: per channel, the sums of da * xhat and of da over
-// the whole batch, from the chunk partials in chunk order.
-__global__ void norm_param_grad_kernel(const float2* __restrict__ part, int nparts, int C,
-                                       float* __restrict__ dgamma, float* __restrict__ dbeta) {
-    const int c = threadIdx.x;
-    if (c >= C) return;
+// the whole batch from the chunk partials (C <= 64, one workgroup of 256 threads): thread
+// (c, l) adds partials l, l + L, ... in order (L = 256 / C), then the lane sums of each
+// channel are added in lane order.
+__global__ void __launch_bounds__(256) norm_param_grad_kernel(const float2* __restrict__ part, int nparts, int C,
+                                                              float* __restrict__ dgamma, float* __restrict__ dbeta) {
+    __shared__ float r0[256], r1[256];
+    const int t = threadIdx.x, L = max(1, 256 / C), c = t % C, l = t / C;
     float s0 = 0.f, s1 = 0.f;
-    for (int i = 0; i < nparts; ++i) {
-        const float2 v = part[static_cast<int64_t>(i) * C + c];
-        s0 += v.x;
-        s1 += v.y;
+    if (l < L)
+#pragma unroll 8
+        for (int i = l; i < nparts; i += L) {
+            const float2 v = part[static_cast<int64_t>(i) * C + c];
+            s0 += v.x;
+            s1 += v.y;
+        }
+    r0[t] = s0;
+    r1[t] = s1;
+    __syncthreads();
+    if (t < C) {
+        float v0 = 0.f, v1 = 0.f;
+        for (int i = 0; i < L; ++i) {
+            v0 += r0[i * C + t];
+            v1 += r1[i * C + t];
+        }
+        dbeta[t] = v0;
+        dgamma[t] = v1;
     }
-    dbeta[c] = s0;
-    dgamma[c] = s1;
 }
 
 // dz = dL/d(conv output before LeakyReLU) over this chunk.
@@ -671,7 +685,7 @@ svdlut_status paper_generator_backward(const float* params, const uint8_t* mask,
         float2* bpart = reinterpret_cast<float2*>(k.part);
         hipLaunchKernelGGL(norm_bwd_stats_kernel, grid, dim3(kNormThreads), 0, st, k.h[i - 1], k.da[i - 1],
                            k.mu[i - 1], k.rs[i - 1], bpart, HW, C);
-        hipLaunchKernelGGL(norm_param_grad_kernel, dim3(1), dim3(64), 0, st, bpart, static_cast<int>(grid.x), C,
+        hipLaunchKernelGGL(norm_param_grad_kernel, dim3(1), dim3(256), 0, st, bpart, static_cast<int>(grid.x), C,
                            G.ng[i - 1], G.nb[i - 1]);
         hipLaunchKernelGGL(norm_bwd_apply_kernel, grid, dim3(kNormThreads), 0, st, k.h[i - 1], k.da[i - 1], bpart,
                            k.mu[i - 1], k.rs[i - 1], P.ng[i - 1], k.dz[i - 1], HW, C);
