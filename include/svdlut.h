@@ -156,6 +156,13 @@ svdlut_status svdlut_unfused_apply(const float* x, float* y, const float* grids,
  *   float32; dbias [B][3] float32.
  * ws: device workspace of at least svdlut_apply_bwd_workspace_size(B, D) bytes, 256-byte
  *   aligned, owned by the caller; contents on entry are ignored.
+ * Errors: EINVAL for a null input, a partial (dU, ds, dV) trio, sizes out of range or a short
+ *   workspace; EUNSUPPORTED for an unknown dtype, or when the map columns that one 256-pixel
+ *   row segment touches cannot be staged in LDS next to T and its fixed-point gradient even
+ *   with 64-thread workgroups.  That happens only for D >= 37 with maps finer than about two
+ *   thirds of the image width at D = 40 (176 columns per segment fit there); for D <= 36
+ *   every map size works (fine maps take narrower workgroups, and their dmap partials go
+ *   straight to global memory when the map-row accumulator does not fit).
  * dT is accumulated in fixed point per workgroup and summed in a fixed order, so dU, ds
  * and dV are reproducible, as is dx; dmap and dbias are summed across workgroups with
  * float atomics and depend on their order at the level of float32 rounding, except in

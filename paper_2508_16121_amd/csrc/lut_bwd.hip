@@ -745,7 +745,10 @@ static svdlut_status launch_bwd_impl(const BwdLaunch& a, const LossArgs* L, hipS
         }
         if (block == 0) mrows = 0;   // too many map columns: send dmap straight to global atomics
     }
-    if (block == 0) return fail(SVDLUT_EUNSUPPORTED, "apply_bwd: map too wide for the LDS staging");
+    if (block == 0)
+        return fail(SVDLUT_EUNSUPPORTED, "apply_bwd: the map columns one 256-pixel segment touches (" +
+                                             std::to_string(P.ncol_max) + ") do not fit the LDS next to T and dT at D = " +
+                                             std::to_string(a.D));
     P.mrows = P.want_dmap ? mrows : 0;
     const size_t lds = bwd_lds(a.D, block, P.ncol_max, P.mrows, a.w, a.R);
     const bool det = a.det && (a.dmap || a.dbias);

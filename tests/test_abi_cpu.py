@@ -272,3 +272,4 @@ def test_deterministic_mode_from_environment():
                            timeout=120)
         assert r.returncode == 0, r.stderr
         assert r.stdout.strip() == want, (val, r.stdout)
+

@@ -106,6 +106,27 @@ def test_backward_fine_maps_at_d33(svd, hw):
     assert np.abs(host(r["dx"]) - ref["dx"]).max() <= dx_bar(G, m, U, s, V, D)
 
 
+def test_backward_map_staging_limit(svd):
+    """Per-pixel maps: at D = 36 the 64-thread workgroup still stages a segment's 259 map
+    columns next to T and dT (parity as usual); at D = 40 they do not fit the LDS and the call
+    is refused with EUNSUPPORTED and a message, not launched."""
+    B, H, W, R = 1, 24, 300, 8
+    g = np.random.default_rng(1234)
+    x = g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)
+    G = g.uniform(-0.25, 0.25, (B, 3, H, W)).astype(np.float32)
+    m = synth.spatial_map(g, B, H, W)
+    U, s, V = synth.factors(g, B, 36, R)
+    say("bwd per-pixel map at D=36")
+    r = svd.apply_bwd(dev(x), dev(G), dev(U), dev(s), dev(V), dev(m), need_bias=True)
+    ref = ol.apply_bwd(x, U, s, V, m, G)
+    for k in ("dU", "ds", "dV", "dmap", "db"):
+        close(host(r[k]), ref[k], 1e-4, k)
+    U, s, V = synth.factors(g, B, 40, R)
+    say("bwd per-pixel map at D=40: refused")
+    with pytest.raises(svd.SvdlutError, match="do not fit the LDS"):
+        svd.apply_bwd(dev(x), dev(G), dev(U), dev(s), dev(V), dev(m))
+
+
 def test_backward_subsets_and_overwrite(svd):
     """Only the requested gradients are produced, and a second call overwrites (no accumulation)."""
     c = synth.single(31, 48, 96, 9, 3, 6, 12)
