@@ -12,8 +12,13 @@
  *    stream) and returns a status.  Arguments are validated before any HIP call; a
  *    rejected call returns SVDLUT_EINVAL (or SVDLUT_EUNSUPPORTED) and enqueues nothing.
  *    A launch failure returns SVDLUT_EDEVICE.  svdlut_last_error() gives a message for
- *    the calling thread's most recent failure.  Faults inside kernels surface at the
- *    caller's next synchronisation.
+ *    the calling thread's most recent failure.  Every launch is checked right after it
+ *    is enqueued (hipGetLastError), so an error the runtime reports at launch time is
+ *    returned by the call that made it, never left for a later one.  An error that
+ *    happens while a kernel runs is not seen by the library: the ROCm runtime reports it
+ *    at the caller's next synchronisation (hipStreamSynchronize and the like), and a GPU
+ *    memory fault terminates the process.  The kernels bound every access by the sizes
+ *    validated here, so such faults are not an expected outcome of valid arguments.
  *  * Channels a in {0: r, 1: g, 2: b}.  Colour pairs p in {0: rg, 1: rb, 2: gb} with
  *    (alpha, beta) = (0,1), (0,2), (1,2).  The nine LUTs of an image, and the nine
  *    channels of its spatial map, are indexed l = 3*c + p for output channel c.
@@ -23,7 +28,7 @@
  *    second (beta): T_l = U_l diag(s_l) V_l^T.  Spatial map [B][9][h][w].
  *  * Gradients are overwritten, never accumulated.
  *  * Limits: 2 <= D <= 40 (the LUTs and their gradients are staged in LDS), 1 <= R <= 64,
- *    1 <= H, W, h, w <= 65535, B >= 1.
+ *    1 <= H, W, h, w <= 65535, B >= 1 (B <= 4096 for the generators).
  */
 #ifndef SVDLUT_H
 #define SVDLUT_H
