@@ -492,6 +492,22 @@ def row_c4(svd, torch, synth, args):
     ms_f = event_time(fwd, steps, 3, torch)
     ms_fb = event_time(fwd_bwd, steps, 3, torch)
     ms_fused = event_time(fused, steps, 3, torch)
+    # the same three passes in deterministic mode (dmap and dbias from per-workgroup partials)
+    was = svd.deterministic()
+    svd.deterministic(True)
+    try:
+        for d in sets:
+            d["dws"] = svd.bwd_workspace(B, 33, "cuda", (H, W, c.smap.shape[2], c.smap.shape[3]))
+
+        def fwd_bwd_det(i):
+            d = sets[i % N_ROT]
+            svd.apply(d["x"], d["U"], d["s"], d["V"], d["smap"], out=d["y"])
+            _, dy = svd.loss(d["y"], d["target"], "l1")
+            svd.apply_bwd(d["x"], dy, d["U"], d["s"], d["V"], d["smap"], ws=d["dws"])
+
+        ms_fb_det = event_time(fwd_bwd_det, steps, 3, torch)
+    finally:
+        svd.deterministic(was)
     # algorithmic bytes: forward 24.56 B/px; loss 24 B/px (y, target read, dy written);
     # backward x 12 + dy 12 + dx 12 B/px plus the map and its gradient
     mapb = B * 9 * 64 * 64 * 4
@@ -501,6 +517,7 @@ def row_c4(svd, torch, synth, args):
             "fwd_ms": round(ms_f, 4), "fwd_bwd_ms": round(ms_fb, 4),
             "fwd_mpix_s": round(npx / (ms_f * 1e-3) / 1e6, 1), "fwd_bwd_mpix_s": round(npx / (ms_fb * 1e-3) / 1e6, 1),
             "fwd_roofline": roof(b_fwd, ms_f), "fwd_bwd_roofline": roof(b_fb, ms_fb),
+            "fwd_bwd_deterministic_ms": round(ms_fb_det, 4),
             # the same step as one fused pass (svdlut_apply_loss_bwd): x, target in; dx out
             "fused_loss_bwd_ms": round(ms_fused, 4), "fused_mpix_s": round(npx / (ms_fused * 1e-3) / 1e6, 1),
             "fused_roofline": roof(npx * 36 + 2 * mapb, ms_fused)}
