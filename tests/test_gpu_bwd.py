@@ -507,3 +507,34 @@ def test_deterministic_mode_grid_backward_bitwise(svd):
         svd.deterministic(was)
     for k in a:
         assert torch.equal(a[k], b[k]), k
+
+
+def test_deterministic_mode_subsets_and_half_storage(svd):
+    """Deterministic mode with half-precision storage (x, dL/dY and the map in fp16) and with
+    dmap or dbias requested alone: repeated calls bitwise equal, and the same values as the
+    default mode to float rounding (1e-6 of the largest entry)."""
+    B, H, W, D, R, h, w = 2, 70, 300, 17, 4, 9, 37
+    say("deterministic mode, fp16 storage and subsets")
+    g = np.random.default_rng(515)
+    x = torch.from_numpy(g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)).cuda().half()
+    G = torch.from_numpy(g.normal(0, 1, (B, 3, H, W)).astype(np.float32)).cuda().half()
+    U, s, V = (dev(a) for a in synth.factors(g, B, D, R))
+    m = dev(synth.spatial_map(g, B, h, w)).half()
+    was = svd.deterministic()
+    try:
+        svd.deterministic(False)
+        base = svd.apply_bwd(x, G, U, s, V, m, need_dx=False, need_factors=False, need_map=True, need_bias=True)
+        svd.deterministic(True)
+        runs = [svd.apply_bwd(x, G, U, s, V, m, need_dx=False, need_factors=False, need_map=True, need_bias=True)
+                for _ in range(2)]
+        only_map = svd.apply_bwd(x, G, U, s, V, m, need_dx=False, need_factors=False, need_map=True)
+        only_bias = svd.apply_bwd(x, G, U, s, V, m, need_dx=False, need_factors=False, need_map=False,
+                                  need_bias=True)
+        torch.cuda.synchronize()
+    finally:
+        svd.deterministic(was)
+    for k in ("dmap", "db"):
+        assert torch.equal(runs[0][k], runs[1][k]), k
+        close(host(runs[0][k]), host(base[k]), 1e-6, k)
+    assert torch.equal(only_map["dmap"], runs[0]["dmap"])
+    assert torch.equal(only_bias["db"], runs[0]["db"])
