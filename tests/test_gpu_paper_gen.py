@@ -171,11 +171,12 @@ def test_paper_generator_backward_parity(PM, K, use_mask, sign):
             # With one LeakyReLU slope per channel the gradient of a bias in front of an
             # instance norm is zero: dz = slope * dh and the norm's dh is mean-free per
             # channel.  Both sides must give zero to rounding, judged per channel against
-            # L1 = sum |dz| over the summed terms.  The GPU's sum has depth <= 16 + 16 + the
-            # number of workgroups (< 200 here), and each fp32 term carries a relative error
-            # of a few u times (1 + |mean / std|) of the norm's input (< 20 here), so 256 u
-            # x L1 (u = 2^-24) is a safe bar; a gradient that is not mean-free is of the
-            # size of sqrt(sum dz^2) >= L1 / sqrt(terms), 300 times that bar or more here.
+            # L1 = sum |dz| over the summed terms.  The GPU's sum has depth <= 16 pixels per
+            # lane + 16 lanes per workgroup + 64 partials per lane of the final sum + 16 lane
+            # sums (< 200 here), and the fp32 dz carries the rounding of the norm's mean terms,
+            # a few u times (1 + |mean / std|) of the norm's input (< 20 here) per term, so
+            # 256 u x L1 (u = 2^-24) is a safe bar; a gradient that is not mean-free is of
+            # the size of sqrt(sum dz^2) >= L1 / sqrt(terms), 300 times that bar or more here.
             assert (np.abs(ref[k]) <= 1e-12 * l1[k]).all(), k
             ratio = np.abs(got[k]) / l1[k]
             say(f"  {k:12s} |gpu| / L1 max {ratio.max():.2e}")
