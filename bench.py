@@ -457,7 +457,7 @@ def row_c3(svd, torch, synth, args):
                         "fp16 storage, D=33 R=8, 1/8 maps, one graph-replayed persistent launch",
             "ms": round(ms, 4), "mpix_s": round(npx / (ms * 1e-3) / 1e6, 1), "roofline": roof(bytes_alg, ms),
             "loop_of_64_apply_ms": round(ms_loop, 4), "speedup_vs_loop": round(ms_loop / ms, 3),
-            "plan": {k: info[k] for k in ("block", "grid", "tuned", "graph")}}
+            "plan": {k: info[k] for k in ("block", "grid", "blocks_per_cu", "tile_px", "px_per_lane", "tuned", "graph")}}
 
 
 def row_c4(svd, torch, synth, args):

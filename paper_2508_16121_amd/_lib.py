@@ -78,7 +78,9 @@ class ImageDesc(C.Structure):
 
 class PlanInfo(C.Structure):
     _fields_ = [("pixels", C.c_int64), ("tiles", C.c_int64), ("block", C.c_int32),
-                ("grid", C.c_int32), ("tuned", C.c_int32), ("graph", C.c_int32)]
+                ("grid", C.c_int32), ("tuned", C.c_int32), ("graph", C.c_int32),
+                ("tile_px", C.c_int32), ("px_per_lane", C.c_int32), ("blocks_per_cu", C.c_int32),
+                ("reserved", C.c_int32)]
 
 
 class SvdlutError(RuntimeError):

@@ -429,7 +429,7 @@ struct svdlut_plan {
     int64_t pixels = 0, tiles = 0;
     int ncol_max = 1;
     int fast_map = 1;
-    int block = 512, grid = 1;
+    int block = 512, grid = 1, bpc = 1;
     int tuned = 0;
     ImgGeom* d_descs = nullptr;
     int64_t* d_tiles = nullptr;
@@ -546,6 +546,7 @@ static bool same_buffers(const ApplyLaunch& a, const ApplyLaunch& b) {
 
 static void plan_set_shape(svdlut_plan* p, int block, int bpc, const DeviceInfo& di) {
     p->block = block;
+    p->bpc = bpc;
     const int64_t max_grid = static_cast<int64_t>(di.cus) * bpc;
     const int64_t min_tiles = block / kWave;
     p->grid = static_cast<int>(std::max<int64_t>(1, std::min(max_grid, (p->tiles + min_tiles - 1) / min_tiles)));
@@ -730,6 +731,10 @@ svdlut_status svdlut_plan_get_info(const svdlut_plan* p, svdlut_plan_info* info)
     info->grid = p->grid;
     info->tuned = p->tuned;
     info->graph = p->have_graph ? 1 : 0;
+    info->tile_px = kSeg;
+    info->px_per_lane = kPxPerLane;
+    info->blocks_per_cu = p->bpc;
+    info->reserved = 0;
     return SVDLUT_OK;
 }
 

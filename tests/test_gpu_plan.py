@@ -70,6 +70,9 @@ def test_plan_small_uneven(svd, io, tol):
     info = plan.info()
     assert info["pixels"] == sum(d["H"] * d["W"] for d in packed[5])
     assert info["graph"] == 1
+    assert (info["tile_px"], info["px_per_lane"]) == (256, 4)
+    assert info["tiles"] == sum(d["H"] * -(-d["W"] // 256) for d in packed[5])
+    assert 1 <= info["blocks_per_cu"] <= 32
 
 
 def test_plan_graph_replay_with_new_buffers(svd):
