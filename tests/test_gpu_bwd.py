@@ -407,7 +407,14 @@ def test_backward_heavy_tailed_inputs(svd, case):
     the rest, or one pixel 1e4 times) or a map with a few large values.  The accumulator grid
     of a workgroup follows the band's sum of |dy| (not pixels x largest |dy|), so the outliers
     must not coarsen the other terms: by linearity the gradient of G + G_out is compared with
-    the oracle to 1e-4 of the largest gradient of the ordinary part G alone."""
+    the oracle to 1e-4 of the largest gradient of the ordinary part G alone, plus the float
+    rounding of the sums that carry the outliers' own magnitude.  That part: dmap and db leave
+    the workgroups as float partials added by atomics (at most 128 per entry here), and dU,
+    ds, dV are float sums of 128 workgroup partials of dT followed by products over D = 33, so
+    each is within gamma_n (n < 256) of the sum of the absolute values of its terms; those
+    sums are the oracle's gradients of |G + G_out| with |U|, |V| (and, for dmap, a LUT of ones
+    times max |T|), the maps being nonnegative.  The bar is 1e-4 x scale + 256 u x that
+    magnitude, elementwise (u = 2^-24)."""
     B, H, W, D, R, h, w = 2, 128, 256, 33, 8, 16, 32
     say(f"bwd heavy tails: {case}")
     g = np.random.default_rng({"sparse outliers": 91, "single spike": 92, "map outliers": 93}[case])
@@ -428,12 +435,22 @@ def test_backward_heavy_tailed_inputs(svd, case):
     r = svd.apply_bwd(dev(x), dev(Gall), dev(U), dev(s), dev(V), dev(m), need_bias=True)
     ref = ol.apply_bwd(x, U, s, V, m, Gall)
     ref_n = ol.apply_bwd(x, U, s, V, m, G)
+    Ga = np.abs(Gall)
+    mag = ol.apply_bwd(x, np.abs(U), s, np.abs(V), m, Ga)
+    ones = np.zeros_like(U)
+    ones[..., 0] = 1.0
+    s1 = np.zeros_like(s)
+    s1[..., 0] = 1.0
+    mag["dmap"] = ol.apply_bwd(x, ones, s1, ones, m, Ga)["dmap"] * np.abs(ol.reconstruct(U, s, V)).max()
     keys = ("dU", "ds", "dV", "dmap", "db") if case != "map outliers" else ("dU", "ds", "dV", "dmap")
     for k in keys:
-        err = np.abs(host(r[k]) - ref[k]).max()
+        err = np.abs(host(r[k]) - ref[k])
         scale = np.abs(ref_n[k] if case != "map outliers" else ref[k]).max()
-        say(f"  {k}: max-abs {err:.3e}, scale {scale:.3e}")
-        assert err <= 1e-4 * scale, k
+        bar = 1e-4 * scale + 256 * 2.0 ** -24 * np.abs(mag[k])
+        i = np.unravel_index(np.argmax(err / bar), err.shape)
+        say(f"  {k}: max-abs {err.max():.3e}, scale {scale:.3e}; worst entry err {err[i]:.3e} "
+            f"against bar {bar[i]:.3e}")
+        assert (err <= bar).all(), k
 
 
 @pytest.mark.parametrize("shape", [
