@@ -563,3 +563,24 @@ def test_deterministic_mode_subsets_and_half_storage(svd):
         assert within(host(runs[0][k]), host(base[k]), bars[k]), k
     assert torch.equal(only_map["dmap"], runs[0]["dmap"])
     assert torch.equal(only_bias["db"], runs[0]["db"])
+
+
+@pytest.mark.parametrize("shape", [
+    (1, 2, 65535, 40, 64, 2, 512),      # the longest row, the largest D and R
+    (1, 65535, 2, 33, 8, 4097, 2),      # the longest column
+])
+def test_backward_maximum_dimensions(svd, shape):
+    """The backward at H or W = 65535 with the largest LUTs: LUT and map gradients against the
+    oracle at 1e-4 of their largest value, dx at the bound of its arithmetic."""
+    B, H, W, D, R, h, w = shape
+    say(f"bwd maximum dims {shape}")
+    g = np.random.default_rng(sum(shape) % 997)
+    x = g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)
+    U, s, V = synth.factors(g, B, D, R)
+    m = synth.spatial_map(g, B, h, w)
+    G = g.uniform(-0.25, 0.25, (B, 3, H, W)).astype(np.float32)
+    r = svd.apply_bwd(dev(x), dev(G), dev(U), dev(s), dev(V), dev(m), need_bias=True)
+    ref = ol.apply_bwd(x, U, s, V, m, G)
+    for k in ("dU", "ds", "dV", "dmap", "db"):
+        close(host(r[k]), ref[k], 1e-4, k)
+    assert np.abs(host(r["dx"]) - ref["dx"]).max() <= dx_bound(G, m, U, s, V, D)

@@ -178,3 +178,22 @@ def test_apply_rejects_bad_arguments(svd):
         svd.apply(x, bad, s[:, :, :4].contiguous(), bad, m)
     with pytest.raises(ValueError):
         svd.apply(x, U, s, V, m[:, :8].contiguous())
+
+
+@pytest.mark.parametrize("shape", [
+    (1, 1, 65535, 40, 64, 1, 65535),    # the longest row, a per-pixel map, the largest D and R
+    (1, 65535, 1, 40, 64, 4097, 1),     # the longest column
+    (1, 3, 65535, 33, 8, 3, 8192),      # a long row over a map with 8 pixels per column
+])
+def test_apply_maximum_dimensions(svd, shape):
+    """H or W at 65535 (the largest the ABI takes) with D = 40 and R = 64: every pixel against
+    the oracle at the fp32 bar."""
+    B, H, W, D, R, h, w = shape
+    say(f"apply maximum dims {shape}")
+    g = np.random.default_rng(sum(shape) % 1000)
+    x = g.uniform(-0.05, 1.05, (B, 3, H, W)).astype(np.float32)
+    U, s, V = synth.factors(g, B, D, R)
+    m = synth.spatial_map(g, B, h, w)
+    y = svd.apply(dev(x), dev(U), dev(s), dev(V), dev(m))
+    ref = ol.apply(x, U, s, V, m)
+    assert np.abs(host(y) - ref).max() <= TOL32
