@@ -240,3 +240,28 @@ def test_plan_fallbacks_and_tuning_cache(tmp_path):
             fixed = json.load(open(cache))          # rewritten as valid JSON
             assert list(fixed) == [key], fixed
         np.testing.assert_array_equal(y, y_ref)
+
+
+def test_plan_degenerate_images(svd):
+    """A batch mixing degenerate images — a single pixel, a single row, a single column, a
+    1 x 1 map, a per-pixel map, widths that are not multiples of 4 — in one plan (fp32): every
+    pixel against the oracle, and the plain launch bit for bit equal to the graph replay."""
+    g = synth.rng(4242)
+    specs = [(1, 1, 1, 1), (1, 300, 1, 7), (257, 1, 9, 1), (33, 65, 1, 1), (40, 70, 40, 70), (7, 518, 3, 65),
+             (64, 256, 8, 32)]
+    images = []
+    for (H, W, h, w) in specs:
+        x = synth.image(g, H, W)
+        U, s, V = synth.factors(g, 1, 33, 8)
+        m = synth.spatial_map(g, 1, h, w)
+        images.append((x, U[0], s[0], V[0], m[0]))
+    packed = synth.pack_uneven(images)
+    say("plan degenerate images")
+    plan, x, m, y, (U, s, V) = run_plan(svd, packed, io=torch.float32)
+    oracle_check(packed, x, m, y, 1e-5)
+    y2 = torch.zeros_like(y)
+    plan.launch_direct(x, y2, U, s, V, m)
+    torch.cuda.synchronize()
+    assert torch.equal(y, y2)
+    info = plan.info()
+    assert info["pixels"] == sum(H * W for (H, W, _, _) in specs)
