@@ -53,6 +53,7 @@ def _check(svd, x, U, s, V, m, gr, gw, gb, bias=None, io=torch.float32, mt=torch
     (1, 1, 300, 5, 2, 1, 38, 6, 2),       # one row, Ds = 2
     (1, 130, 1, 5, 2, 17, 1, 12, 33),     # one column, K = 12, Ds = 33
     (3, 20, 20, 9, 3, 15, 15, 6, 9),      # per-pixel map path, batch of three
+    (1, 1, 65535, 40, 64, 1, 8192, 12, 33),   # the longest row, the largest D, R, K and Ds
 ])
 def test_apply_grid_parity(svd, shape):
     B, H, W, D, R, h, w, K, Ds = shape
@@ -149,6 +150,7 @@ def _check_bwd(svd, shape, seed, io=torch.float32, rel=1e-4):
     (2, 37, 131, 33, 8, 5, 17, 6, 17),    # ragged, width not a multiple of 4
     (1, 20, 24, 9, 3, 15, 15, 3, 9),      # more than one grid vertex per pixel step (tiny image)
     (1, 1, 300, 5, 2, 1, 38, 6, 2),       # one row, Ds = 2
+    (1, 2, 4099, 33, 8, 2, 513, 12, 33),  # the largest K and Ds, a long ragged row
 ])
 def test_apply_grid_bwd_parity(svd, shape):
     _check_bwd(svd, shape, seed=sum(shape) + 7)
