@@ -333,6 +333,71 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
     }
 }
 
+// Per-channel sums of |dy| and the largest |dy| over [0, n) of the three channel planes
+// starting at p (plane stride `plane`), all three walked together so that a thread's loads
+// of the three planes are in flight at once.  Each channel's sum takes its values in the
+// same order as abssum_range would.
+template <typename IO>
+__device__ inline void scan_dy3(const IO* p, int64_t plane, int64_t n, float (&s)[3], float& m, bool& bad) {
+    const bool vec = ((plane & 3) == 0) && (reinterpret_cast<uintptr_t>(p) & (4 * sizeof(IO) - 1)) == 0;
+    if (!vec) {
+        for (int c = 0; c < 3; ++c) abssum_range<IO>(p + c * plane, n, s[c], m, bad);
+        return;
+    }
+    const int64_t n4 = n / 4, step = blockDim.x;
+    int64_t v = threadIdx.x;
+    for (; v + 3 * step < n4; v += 4 * step) {
+        float q[3][4][4];
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) ld4<IO>(p + c * plane + 4 * (v + u * step), q[c][u]);
+#pragma unroll
+        for (int c = 0; c < 3; ++c)
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) abssum_acc(q[c][u][e], s[c], m, bad);
+    }
+    for (; v < n4; v += step)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            float q[4];
+            ld4<IO>(p + c * plane + 4 * v, q);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) abssum_acc(q[e], s[c], m, bad);
+        }
+    for (int64_t i = n4 * 4 + threadIdx.x; i < n; i += blockDim.x)
+#pragma unroll
+        for (int c = 0; c < 3; ++c) abssum_acc(ldf<IO>(p + c * plane + i), s[c], m, bad);
+}
+
+// Largest |value| over the first n entries of nine map planes (stride mplane) from p: one
+// flat walk over the 9n entries with eight loads per thread in flight (the band's map rows
+// are short, so a walk per plane would wait for nine rounds of loads).
+template <typename MT>
+__device__ inline void scan_map9(const MT* p, int64_t mplane, int64_t n, float& m, bool& bad) {
+    if (9 * n > INT32_MAX) {
+        for (int l = 0; l < 9; ++l) absmax_range<MT>(p + l * mplane, n, m, bad);
+        return;
+    }
+    const uint32_t n32 = static_cast<uint32_t>(n), total = 9u * n32, step = blockDim.x;
+    for (uint32_t e0 = threadIdx.x; e0 < total; e0 += 8 * step) {
+        float q[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const uint32_t e = e0 + u * step;
+            q[u] = 0.f;
+            if (e < total) {
+                const uint32_t l = e / n32;
+                q[u] = ldf<MT>(p + l * mplane + (e - l * n32));
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) absmax_acc(q[u], m, bad);
+    }
+}
+
 template <typename IO, typename MT, bool FASTMAP, int LOSS>
 __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
     extern __shared__ float smem[];
@@ -395,32 +460,51 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
         // only receives terms of output channel l / 3) and its maximum.  L1: |dy| = 1/n at
         // most.  MSE: |dy| = 2 |y - t| / n with |y_c| <= 3 max|map| max|T| + |b_c| and the
         // band's sums and maximum of |t| (the dy buffer holds the target).
-        if (LOSS != 1)
-            for (int c = 0; c < 3; ++c) abssum_range<IO>(dyb + c * plane + e0, e1 - e0, sdy[c], mdy, nf);
+        if (LOSS != 1) scan_dy3<IO>(dyb + e0, plane, e1 - e0, sdy, mdy, nf);
         if (P.want_dT || LOSS == 2) {
             const int64_t mplane = static_cast<int64_t>(a.h) * a.w;
             const MT* mb = reinterpret_cast<const MT*>(a.map) + static_cast<int64_t>(b) * 9 * mplane +
                            static_cast<int64_t>(row_lo) * a.w;
-            for (int l = 0; l < 9; ++l)
-                absmax_range<MT>(mb + l * mplane, static_cast<int64_t>(row_hi - row_lo + 1) * a.w, mmap, nf);
+            scan_map9<MT>(mb, mplane, static_cast<int64_t>(row_hi - row_lo + 1) * a.w, mmap, nf);
         }
         if (P.want_dmap || LOSS == 2) {
+            // every vertex row of the three pairs: D * kNode contiguous values
             const int RS = lut_row_stride(D), PS = lut_pair_stride(D);
-            for (int e = threadIdx.x; e < 9 * D * D; e += blockDim.x) {
-                const int l = e / (D * D), r = e - l * (D * D);
-                const int i = r / D, jj = r - i * D;
-                const float v = fabsf(Tl[(l % 3) * PS + i * RS + kNode * jj + l / 3]);
-                nf |= !(v <= FLT_MAX);
-                mT = fmaxf(mT, v);
+            for (int r = wave; r < 3 * D; r += nw) {
+                const int p = r / D;
+                const float* row = Tl + p * PS + (r - p * D) * RS;
+                for (int k = threadIdx.x & (kWave - 1); k < D * kNode; k += kWave) {
+                    const float v = fabsf(row[k]);
+                    nf |= !(v <= FLT_MAX);
+                    mT = fmaxf(mT, v);
+                }
             }
         }
-        mdy = block_max(mdy, aux);
+        // one block-wide reduction of the seven values (lanes by butterfly, then waves in order)
+        float red[7] = {mdy, sdy[0], sdy[1], sdy[2], mmap, mT, nf ? 1.f : 0.f};
+#pragma unroll
+        for (int k = 0; k < 7; ++k)
+            for (int off = 32; off > 0; off >>= 1) {
+                const float o = __shfl_xor(red[k], off, 64);
+                red[k] = (k >= 1 && k <= 3) ? red[k] + o : fmaxf(red[k], o);
+            }
+        if ((threadIdx.x & (kWave - 1)) == 0)
+#pragma unroll
+            for (int k = 0; k < 7; ++k) aux[wave * 8 + k] = red[k];
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 7; ++k) {
+            float m = aux[k];
+            for (int i = 1; i < nw; ++i) m = (k >= 1 && k <= 3) ? m + aux[i * 8 + k] : fmaxf(m, aux[i * 8 + k]);
+            red[k] = m;
+        }
+        __syncthreads();   // aux is the waves' staging area from here on
+        mdy = red[0];
         float sdm = 0.f;
-        if (LOSS != 1)
-            for (int c = 0; c < 3; ++c) sdm = fmaxf(sdm, block_sum(sdy[c], aux));
-        mmap = block_max(mmap, aux);
-        mT = block_max(mT, aux);
-        bad = block_max(nf ? 1.f : 0.f, aux) > 0.f;
+        if (LOSS != 1) sdm = fmaxf(red[1], fmaxf(red[2], red[3]));
+        mmap = red[4];
+        mT = red[5];
+        bad = red[6] > 0.f;
         const float n = static_cast<float>((t1 - t0) * kSeg);   // band pixels (padding included)
         if (LOSS == 1) {
             mdy = P.inv_n;
@@ -545,7 +629,8 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
 }
 
 // loss = inv_n * sum of the per-workgroup partials, in order (fp64).
-__global__ void loss_sum_kernel(const float* __restrict__ part, int n, float inv_n, float* __restrict__ out) {
+// (run by the first wave of a workgroup)
+__device__ inline void loss_sum(const float* __restrict__ part, int n, float inv_n, float* __restrict__ out) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < n; i += 64) acc += part[i];
     for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
@@ -556,12 +641,9 @@ __global__ void loss_sum_kernel(const float* __restrict__ part, int n, float inv
 // order.  The workgroups of an image cover consecutive bands, so their first map rows rowlo
 // do not decrease with the workgroup index; the ones whose accumulator [rowlo, rowlo + mrows)
 // holds row r form a run found by a binary search.  Workgroups without rows carry rowlo = h.
-__global__ void __launch_bounds__(256) det_reduce_kernel(const int* __restrict__ rowlo,
-                                                         const float* __restrict__ mpart,
-                                                         const float* __restrict__ dbpart, float* __restrict__ dmap,
-                                                         float* __restrict__ dbias, int B, int gpi, int mrows, int h,
-                                                         int w) {
-    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+__device__ inline void det_reduce_item(int64_t i, const int* __restrict__ rowlo, const float* __restrict__ mpart,
+                                       const float* __restrict__ dbpart, float* __restrict__ dmap,
+                                       float* __restrict__ dbias, int B, int gpi, int mrows, int h, int w) {
     const int64_t nmap = dmap ? static_cast<int64_t>(B) * 9 * h * w : 0;
     if (i < nmap) {
         const int col = static_cast<int>(i % w);
@@ -589,14 +671,11 @@ __global__ void __launch_bounds__(256) det_reduce_kernel(const int* __restrict__
 
 // Sum the per-workgroup dT partials (fixed order) and apply the chain rule of
 // T = U diag(s) V^T: dU = dT V diag(s), dV = dT^T U diag(s), ds_k = sum_i U_ik (dT V)_ik.
-__global__ void __launch_bounds__(256) factor_grad_kernel(const float* __restrict__ part, int gpi,
-                                                          const float* __restrict__ U,
-                                                          const float* __restrict__ s,
-                                                          const float* __restrict__ V,
-                                                          float* __restrict__ dU, float* __restrict__ ds,
-                                                          float* __restrict__ dV, int D, int R) {
-    extern __shared__ float sm[];
-    const int bl = blockIdx.x;          // b*9 + l
+__device__ inline void factor_grad_block(int bl, float* sm, const float* __restrict__ part, int gpi,
+                                         const float* __restrict__ U, const float* __restrict__ s,
+                                         const float* __restrict__ V, float* __restrict__ dU,
+                                         float* __restrict__ ds, float* __restrict__ dV, int D, int R) {
+    // bl = b*9 + l
     const int b = bl / 9, l = bl - 9 * (bl / 9);
     const int c = l / 3, p = l - 3 * (l / 3);
     const int nlut = lut_floats(D);
@@ -610,15 +689,15 @@ __global__ void __launch_bounds__(256) factor_grad_kernel(const float* __restric
     for (int e = threadIdx.x; e < D * D; e += blockDim.x) {
         const int i = e / D, jj = e - (e / D) * D;
         const float* src = part + static_cast<size_t>(b) * gpi * nlut + lut_slot(p, i, jj, c, D);
-        // fixed summation order; eight independent loads in flight per step
+        // fixed summation order; sixteen independent loads in flight per step
         float acc = 0.f;
         int g = 0;
-        for (; g + 8 <= gpi; g += 8) {
-            float v[8];
+        for (; g + 16 <= gpi; g += 16) {
+            float v[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) v[u] = src[static_cast<size_t>(g + u) * nlut];
+            for (int u = 0; u < 16; ++u) v[u] = src[static_cast<size_t>(g + u) * nlut];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) acc += v[u];
+            for (int u = 0; u < 16; ++u) acc += v[u];
         }
         for (; g < gpi; ++g) acc += src[static_cast<size_t>(g) * nlut];
         dT[e] = acc;
@@ -644,10 +723,56 @@ __global__ void __launch_bounds__(256) factor_grad_kernel(const float* __restric
     }
 }
 
-__global__ void zero_kernel(float* p, int64_t n) {
-    for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
-         i += static_cast<int64_t>(gridDim.x) * blockDim.x)
-        p[i] = 0.f;
+// Everything that runs after the backward's main kernel, in one launch of 1024-thread
+// workgroups: workgroups [0, nfac) sum the dT partials of one LUT channel each and form dU,
+// ds, dV; the next nred workgroups (deterministic mode) form dmap and dbias from their
+// partials, 1024 entries each; one last workgroup (fused loss) sums the loss partials.
+struct PostArgs {
+    int nfac, nred, with_loss;
+    const float* part; int gpi;
+    const float *U, *s, *V;
+    float *dU, *ds, *dV;
+    int D, R;
+    const int* rowlo; const float *mpart, *dbpart;
+    float *dmap, *dbias;
+    int B, mrows, h, w;
+    const float* lpart; int nlp; float inv_n; float* loss;
+};
+
+__global__ void __launch_bounds__(1024) bwd_post_kernel(PostArgs A) {
+    extern __shared__ float sm[];
+    int bid = blockIdx.x;
+    if (bid < A.nfac) {
+        factor_grad_block(bid, sm, A.part, A.gpi, A.U, A.s, A.V, A.dU, A.ds, A.dV, A.D, A.R);
+        return;
+    }
+    bid -= A.nfac;
+    if (bid < A.nred) {
+        det_reduce_item(static_cast<int64_t>(bid) * blockDim.x + threadIdx.x, A.rowlo, A.mpart, A.dbpart, A.dmap,
+                        A.dbias, A.B, A.gpi, A.mrows, A.h, A.w);
+        return;
+    }
+    if (A.with_loss && threadIdx.x < kWave) loss_sum(A.lpart, A.nlp, A.inv_n, A.loss);
+}
+
+// Clears p[0, n) and q[0, m) (either may be empty) in one launch: 16-byte stores over the
+// 16-byte-aligned body of each range, element stores for its ends.
+__device__ inline void zero_range(float* p, int64_t n, int64_t tid, int64_t nthr) {
+    if (n <= 0) return;
+    const int64_t head = std::min<int64_t>(n, ((16 - (reinterpret_cast<uintptr_t>(p) & 15)) & 15) / 4);
+    const int64_t n4 = (n - head) / 4;
+    float4* b = reinterpret_cast<float4*>(p + head);
+    for (int64_t i = tid; i < n4; i += nthr) b[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (tid < head) p[tid] = 0.f;
+    const int64_t t0 = head + 4 * n4;
+    if (tid < n - t0) p[t0 + tid] = 0.f;
+}
+
+__global__ void zero_kernel(float* p, int64_t n, float* q, int64_t m) {
+    const int64_t tid = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    const int64_t nthr = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    zero_range(p, n, tid, nthr);
+    zero_range(q, m, tid, nthr);
 }
 
 }  // namespace
@@ -762,10 +887,13 @@ static svdlut_status launch_bwd_impl(const BwdLaunch& a, const LossArgs* L, hipS
         P.dbpart = a.dbias ? reinterpret_cast<float*>(base + L.dbpart) : nullptr;
         P.mpart = a.dmap ? reinterpret_cast<float*>(base + L.mpart) : nullptr;
     } else {
-        if (a.dmap) hipLaunchKernelGGL(zero_kernel, dim3(256), dim3(256), 0, st, a.dmap,
-                                       static_cast<int64_t>(a.B) * 9 * a.h * a.w);
-        if (a.dbias) hipLaunchKernelGGL(zero_kernel, dim3(1), dim3(64), 0, st, a.dbias,
-                                        static_cast<int64_t>(a.B) * 3);
+        const int64_t nm = a.dmap ? static_cast<int64_t>(a.B) * 9 * a.h * a.w : 0;
+        const int64_t nb = a.dbias ? static_cast<int64_t>(a.B) * 3 : 0;
+        if (nm + nb > 0) {
+            const int64_t blocks = std::min<int64_t>(1024, (std::max(nm / 4, nb) + 255) / 256 + 1);
+            hipLaunchKernelGGL(zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, st, a.dmap, nm,
+                               a.dbias, nb);
+        }
     }
     const int grid = a.B * P.gpi;
 #define SVDLUT_BWD_L(IO, MT, LS)                                                                \
@@ -790,23 +918,29 @@ static svdlut_status launch_bwd_impl(const BwdLaunch& a, const LossArgs* L, hipS
 #undef SVDLUT_BWD_L
     svdlut_status stt = check_launch("apply_bwd");
     if (stt != SVDLUT_OK) return stt;
+    PostArgs Q{};
+    Q.nfac = P.want_dT ? a.B * 9 : 0;
+    Q.part = a.dT; Q.gpi = P.gpi;
+    Q.U = a.U; Q.s = a.s; Q.V = a.V;
+    Q.dU = a.dU; Q.ds = a.ds; Q.dV = a.dV;
+    Q.D = a.D; Q.R = a.R;
     if (det) {
         const int64_t n = (a.dmap ? static_cast<int64_t>(a.B) * 9 * a.h * a.w : 0) + (a.dbias ? 3 * a.B : 0);
-        hipLaunchKernelGGL(det_reduce_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
-                           P.rowlo, P.mpart, P.dbpart, a.dmap, a.dbias, a.B, P.gpi, P.mrows, a.h, a.w);
-        stt = check_launch("apply_bwd deterministic reduction");
-        if (stt != SVDLUT_OK) return stt;
+        Q.nred = static_cast<int>((n + 1023) / 1024);
+        Q.rowlo = P.rowlo; Q.mpart = P.mpart; Q.dbpart = P.dbpart;
+        Q.dmap = a.dmap; Q.dbias = a.dbias;
+        Q.B = a.B; Q.mrows = P.mrows; Q.h = a.h; Q.w = a.w;
     }
     if (L) {
-        hipLaunchKernelGGL(loss_sum_kernel, dim3(1), dim3(64), 0, st, L->lpart, grid, P.inv_n, L->loss);
-        stt = check_launch("apply_loss_bwd");
-        if (stt != SVDLUT_OK) return stt;
+        Q.with_loss = 1;
+        Q.lpart = L->lpart; Q.nlp = grid; Q.inv_n = P.inv_n; Q.loss = L->loss;
     }
-    if (P.want_dT) {
-        const size_t lds2 = sizeof(float) * (static_cast<size_t>(a.D) * a.D + 3 * static_cast<size_t>(a.D) * a.R);
-        hipLaunchKernelGGL(factor_grad_kernel, dim3(a.B * 9), dim3(256), lds2, st, a.dT, P.gpi,
-                           a.U, a.s, a.V, a.dU, a.ds, a.dV, a.D, a.R);
-        stt = check_launch("factor_grad");
+    const int nblk = Q.nfac + Q.nred + Q.with_loss;
+    if (nblk > 0) {
+        const size_t lds2 = Q.nfac ? sizeof(float) * (static_cast<size_t>(a.D) * a.D +
+                                                      3 * static_cast<size_t>(a.D) * a.R) : 0;
+        hipLaunchKernelGGL(bwd_post_kernel, dim3(nblk), dim3(1024), lds2, st, Q);
+        stt = check_launch("apply_bwd (factor gradients, reductions)");
     }
     return stt;
 }
