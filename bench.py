@@ -109,7 +109,7 @@ def mfma_counters():
 
 
 TRACE_FILE = os.path.join(ROOT, "profiles", "apply_4k_fp32_kernel_trace.json")
-HEADLINE_KERNEL = "apply_kernel<float, float, true, false, false>"
+HEADLINE_KERNEL = "apply_kernel<float, float, true, false, false, 4>"
 
 
 def _current_summary(path):

@@ -281,21 +281,25 @@ typedef struct {
     int32_t grid;          /* workgroups in the persistent launch */
     int32_t tuned;         /* 1 if the shape came from the autotuner */
     int32_t graph;         /* 1 if launches replay a captured HIP graph */
-    int32_t tile_px;       /* pixels of one work tile: a row segment handled by one wave */
-    int32_t px_per_lane;   /* consecutive pixels of a tile per lane */
+    int32_t tile_px;       /* pixels of one work tile: a row segment handled by one wave (256 or 512) */
+    int32_t px_per_lane;   /* consecutive pixels of a tile per lane (4 or 8) */
     int32_t blocks_per_cu; /* resident workgroups per CU the grid was sized for */
     int32_t reserved;
 } svdlut_plan_info;
 
 svdlut_status svdlut_plan_create(const svdlut_image_desc* descs, int32_t B, int32_t D, int32_t R,
                                  svdlut_dtype io, svdlut_dtype map_dt, svdlut_plan** out);
-/* The tile is fixed at one 256-pixel row segment per wave, 4 pixels per lane: 8 pixels per
- * lane over 512-pixel segments measured 20-26 % slower on a 4K frame (fewer tiles to spread,
- * half-empty last segments), so the autotuner searches the workgroup size and the number of
- * workgroups per CU.
- * Time each candidate workgroup shape on the given buffers (outputs are overwritten),
- * keep the fastest, record it in the tuning cache (saved to the JSON file named by the
- * SVDLUT_TUNE_CACHE environment variable when set), and rebuild the graph. */
+/* Launch shapes.  A tile is one row segment handled by one wave: 4 consecutive pixels per
+ * lane (256-pixel segments), or 8 (512-pixel segments; only when every image's map is coarse
+ * enough that a lane's 8 pixels lie within two map cells, (8-1)(w-1) <= W-1, built for
+ * workgroups of at most 512 threads).  The autotuner times every valid combination of tile
+ * width, workgroup size (64 .. 1024 threads) and workgroups per CU (powers of two and the
+ * most that fit) on the given buffers (outputs are overwritten), keeps the fastest, records
+ * it in the tuning cache (saved as JSON to the file named by the SVDLUT_TUNE_CACHE
+ * environment variable when set; entries [block, blocks_per_cu, px_per_lane]) and rebuilds
+ * the graph.  The two tile widths compute the map weights of a pixel from different staged
+ * columns, so their outputs agree to rounding, not bit for bit; the workgroup shape alone
+ * does not change any pixel's arithmetic. */
 svdlut_status svdlut_plan_autotune(svdlut_plan* plan, const void* x, void* y,
                                    const float* U, const float* s, const float* V,
                                    const void* map, const float* bias, hipStream_t stream);
@@ -306,6 +310,14 @@ svdlut_status svdlut_plan_launch(svdlut_plan* plan, const void* x, void* y,
 svdlut_status svdlut_plan_launch_direct(svdlut_plan* plan, const void* x, void* y,
                                         const float* U, const float* s, const float* V,
                                         const void* map, const float* bias, hipStream_t stream);
+/* Set the launch shape by hand (as the autotuner would): block threads per workgroup (64,
+ * 128, 256, 512 or 1024), blocks_per_cu workgroups per CU (1 .. 32), px_per_lane 4 or 8.
+ * EINVAL for values outside those sets, EUNSUPPORTED for a shape this batch cannot run (a
+ * workgroup larger than the kernel variant allows, more workgroups per CU than fit the LDS,
+ * or 8 pixels per lane with a map too fine for it); the plan is unchanged then.  A new shape
+ * drops the captured graph; the next launch captures it again. */
+svdlut_status svdlut_plan_set_shape(svdlut_plan* plan, int32_t block, int32_t blocks_per_cu,
+                                    int32_t px_per_lane);
 svdlut_status svdlut_plan_get_info(const svdlut_plan* plan, svdlut_plan_info* info);
 svdlut_status svdlut_plan_destroy(svdlut_plan* plan);
 

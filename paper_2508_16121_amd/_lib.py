@@ -48,6 +48,7 @@ SIGS = {
     "svdlut_plan_autotune": (I32, [P, P, P, P, P, P, P, P, P]),
     "svdlut_plan_launch": (I32, [P, P, P, P, P, P, P, P, P]),
     "svdlut_plan_launch_direct": (I32, [P, P, P, P, P, P, P, P, P]),
+    "svdlut_plan_set_shape": (I32, [P, I32, I32, I32]),
     "svdlut_plan_get_info": (I32, [P, P]),
     "svdlut_plan_destroy": (I32, [P]),
     "svdlut_loss_workspace_size": (SZ, [I64]),

@@ -236,6 +236,7 @@ static svdlut_status apply_impl(const void* x, void* y, svdlut_dtype io, const f
     a.total_tiles = static_cast<int64_t>(B) * H * ((W + kSeg - 1) / kSeg);
     a.ncol_max = map_cols_bound(W, w);
     a.fast_map = map_fast_ok(W, w) ? 1 : 0;
+    a.px = kPxPerLane;
     a.grids = grids; a.gw = gw; a.gb = gb; a.K = K; a.Ds = Ds;
     const int lds_ds = K > 0 ? Ds : 0;
     const int maxb = apply_max_block(io, a.fast_map != 0, K > 0);
@@ -425,14 +426,20 @@ struct svdlut_plan {
     int B = 0, D = 0, R = 0;
     svdlut_dtype io = SVDLUT_F32, map_dt = SVDLUT_F32;
     std::vector<ImgGeom> descs;
-    std::vector<int64_t> tile_start;      // B+1
-    int64_t pixels = 0, tiles = 0;
+    // per tile width (index 0: 4 pixels per lane, 256-pixel segments; 1: 8, 512-pixel
+    // segments): prefix of each image's tiles [B+1], tile count, staged map columns per wave
+    std::vector<int64_t> tile_start[2];
+    int64_t tiles_w[2] = {0, 0};
+    int ncol_w[2] = {1, 1};
+    int fast_map = 1;                     // 4 pixels per lane: every map allows the piecewise path
+    int wide_ok = 1;                      // 8 pixels per lane allowed (piecewise path at that width)
+    int64_t pixels = 0, tiles = 0;        // tiles and ncol_max of the current shape
     int ncol_max = 1;
-    int fast_map = 1;
+    int px = svdlut::kPxPerLane;
     int block = 512, grid = 1, bpc = 1;
     int tuned = 0;
     ImgGeom* d_descs = nullptr;
-    int64_t* d_tiles = nullptr;
+    int64_t* d_tiles[2] = {nullptr, nullptr};
     int device = 0;
     // graph state
     hipGraph_t graph = nullptr;
@@ -486,9 +493,11 @@ static ApplyLaunch plan_args(const svdlut_plan* p, const void* x, void* y, const
     a.x = x; a.y = y; a.U = U; a.s = s; a.V = V; a.map = map; a.bias = bias;
     a.B = p->B; a.D = p->D; a.R = p->R;
     a.H = a.W = a.h = a.w = 0;
-    a.descs = p->d_descs; a.tile_start = p->d_tiles;
+    const int wi = p->px == kPxWide ? 1 : 0;
+    a.descs = p->d_descs; a.tile_start = p->d_tiles[wi];
     a.total_tiles = p->tiles;
-    a.ncol_max = p->ncol_max; a.fast_map = p->fast_map;
+    a.ncol_max = p->ncol_max; a.fast_map = wi ? 1 : p->fast_map;
+    a.px = p->px;
     a.block = p->block; a.grid = p->grid;
     a.io = p->io; a.map_dt = p->map_dt;
     return a;
@@ -541,10 +550,28 @@ static svdlut_status plan_capture(svdlut_plan* p, const ApplyLaunch& a) {
 
 static bool same_buffers(const ApplyLaunch& a, const ApplyLaunch& b) {
     return a.x == b.x && a.y == b.y && a.U == b.U && a.s == b.s && a.V == b.V && a.map == b.map &&
-           a.bias == b.bias && a.block == b.block && a.grid == b.grid;
+           a.bias == b.bias && a.block == b.block && a.grid == b.grid && a.px == b.px;
 }
 
-static void plan_set_shape(svdlut_plan* p, int block, int bpc, const DeviceInfo& di) {
+// Whether a launch shape is valid for the plan: workgroup size and count within the kernel
+// variant's limits and the LDS, 8 pixels per lane only where every map allows it.
+static bool plan_shape_ok(const svdlut_plan* p, int block, int bpc, int px, const DeviceInfo& di) {
+    if (px != kPxPerLane && px != kPxWide) return false;
+    if (px == kPxWide && !p->wide_ok) return false;
+    const int wi = px == kPxWide ? 1 : 0;
+    const bool fast = wi ? true : p->fast_map != 0;
+    const int maxthr = apply_max_block(p->io, fast, false, px);
+    if (!tune_entry_ok(TuneEntry{block, bpc, px}) || block > maxthr) return false;
+    if (apply_lds_bytes(p->D, p->R, block, p->ncol_w[wi]) > static_cast<size_t>(di.lds_per_block)) return false;
+    return bpc <= blocks_per_cu(p->D, p->R, block, p->ncol_w[wi], di, 0, maxthr);
+}
+
+static void plan_set_shape(svdlut_plan* p, int block, int bpc, int px, const DeviceInfo& di) {
+    const int wi = px == kPxWide ? 1 : 0;
+    if (px != p->px || block != p->block || bpc != p->bpc) plan_drop_graph(p);   // another kernel or grid
+    p->px = wi ? kPxWide : kPxPerLane;
+    p->tiles = p->tiles_w[wi];
+    p->ncol_max = p->ncol_w[wi];
     p->block = block;
     p->bpc = bpc;
     const int64_t max_grid = static_cast<int64_t>(di.cus) * bpc;
@@ -567,8 +594,9 @@ svdlut_status svdlut_plan_create(const svdlut_image_desc* descs, int32_t B, int3
     auto p = new svdlut_plan();
     p->B = B; p->D = D; p->R = R; p->io = io; p->map_dt = map_dt;
     p->descs.resize(B);
-    p->tile_start.resize(B + 1);
-    int64_t t = 0;
+    p->tile_start[0].resize(B + 1);
+    p->tile_start[1].resize(B + 1);
+    int64_t t = 0, t8 = 0;
     for (int b = 0; b < B; ++b) {
         const svdlut_image_desc& d = descs[b];
         if (!dims_ok(d.H) || !dims_ok(d.W) || !dims_ok(d.h) || !dims_ok(d.w) || d.x_off < 0 || d.y_off < 0 ||
@@ -577,14 +605,20 @@ svdlut_status svdlut_plan_create(const svdlut_image_desc* descs, int32_t B, int3
             return fail(SVDLUT_EINVAL, "plan_create: descriptor " + std::to_string(b) + " out of range");
         }
         p->descs[b] = ImgGeom{d.H, d.W, d.h, d.w, d.x_off, d.y_off, d.map_off};
-        p->tile_start[b] = t;
+        p->tile_start[0][b] = t;
+        p->tile_start[1][b] = t8;
         t += static_cast<int64_t>(d.H) * ((d.W + kSeg - 1) / kSeg);
+        t8 += static_cast<int64_t>(d.H) * ((d.W + kWave * kPxWide - 1) / (kWave * kPxWide));
         p->pixels += static_cast<int64_t>(d.H) * d.W;
-        p->ncol_max = std::max(p->ncol_max, map_cols_bound(d.W, d.w));
+        p->ncol_w[0] = std::max(p->ncol_w[0], map_cols_bound(d.W, d.w));
+        p->ncol_w[1] = std::max(p->ncol_w[1], map_cols_bound(d.W, d.w, kPxWide));
         if (!map_fast_ok(d.W, d.w)) p->fast_map = 0;
+        if (!map_fast_ok(d.W, d.w, kPxWide)) p->wide_ok = 0;
     }
-    p->tile_start[B] = t;
-    p->tiles = t;
+    p->tile_start[0][B] = t;
+    p->tile_start[1][B] = t8;
+    p->tiles_w[0] = t;
+    p->tiles_w[1] = t8;
     const DeviceInfo& di = device_info();
     p->device = di.device;
     const std::string key = tune_key(p, di);
@@ -593,31 +627,36 @@ svdlut_status svdlut_plan_create(const svdlut_image_desc* descs, int32_t B, int3
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
-        if (it != g_tune.end() && it->second.block <= maxb &&
-            apply_lds_bytes(D, R, it->second.block, p->ncol_max) <= static_cast<size_t>(di.lds_per_block)) {
-            plan_set_shape(p, it->second.block, it->second.bpc, di);
+        if (it != g_tune.end() && plan_shape_ok(p, it->second.block, it->second.bpc, it->second.px, di)) {
+            plan_set_shape(p, it->second.block, it->second.bpc, it->second.px, di);
             p->tuned = 1;
         }
     }
     if (!p->tuned) {
-        const int blk = default_block(D, R, p->ncol_max, di, 0, maxb);
+        const int blk = default_block(D, R, p->ncol_w[0], di, 0, maxb);
         if (blk == 0) {
             delete p;
             return fail(SVDLUT_EUNSUPPORTED, "plan_create: map too wide for LDS staging");
         }
-        plan_set_shape(p, blk, blocks_per_cu(D, R, blk, p->ncol_max, di, 0, maxb), di);
+        plan_set_shape(p, blk, blocks_per_cu(D, R, blk, p->ncol_w[0], di, 0, maxb), kPxPerLane, di);
     }
     if (hipMalloc(reinterpret_cast<void**>(&p->d_descs), sizeof(ImgGeom) * B) != hipSuccess ||
-        hipMalloc(reinterpret_cast<void**>(&p->d_tiles), sizeof(int64_t) * (B + 1)) != hipSuccess) {
+        hipMalloc(reinterpret_cast<void**>(&p->d_tiles[0]), sizeof(int64_t) * (B + 1)) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void**>(&p->d_tiles[1]), sizeof(int64_t) * (B + 1)) != hipSuccess) {
         (void)hipGetLastError();
         if (p->d_descs) (void)hipFree(p->d_descs);
+        if (p->d_tiles[0]) (void)hipFree(p->d_tiles[0]);
         delete p;
         return fail(SVDLUT_ENOMEM, "plan_create: device table allocation failed");
     }
     if (hipMemcpy(p->d_descs, p->descs.data(), sizeof(ImgGeom) * B, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(p->d_tiles, p->tile_start.data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        hipMemcpy(p->d_tiles[0], p->tile_start[0].data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice) !=
+            hipSuccess ||
+        hipMemcpy(p->d_tiles[1], p->tile_start[1].data(), sizeof(int64_t) * (B + 1), hipMemcpyHostToDevice) !=
+            hipSuccess) {
         (void)hipFree(p->d_descs);
-        (void)hipFree(p->d_tiles);
+        (void)hipFree(p->d_tiles[0]);
+        (void)hipFree(p->d_tiles[1]);
         delete p;
         return fail(SVDLUT_EDEVICE, "plan_create: descriptor upload failed");
     }
@@ -676,15 +715,21 @@ svdlut_status svdlut_plan_autotune(svdlut_plan* p, const void* x, void* y, const
                                    const float* V, const void* map, const float* bias, hipStream_t stream) {
     SVDLUT_TRY(check_plan_ptrs(p, x, y, U, s, V, map));
     const DeviceInfo& di = device_info();
-    struct Cand { int block, bpc; };
+    // candidates: tile width (4 pixels per lane, and 8 where every map allows it) x
+    // workgroup size x workgroups per CU (powers of two and the most that fit)
+    struct Cand { int block, bpc, px; };
     std::vector<Cand> cands;
-    const int maxthr = apply_max_block(p->io, p->fast_map != 0, false);
-    for (int blk : {64, 128, 256, 512, 1024}) {
-        if (blk > maxthr) continue;
-        if (apply_lds_bytes(p->D, p->R, blk, p->ncol_max) > static_cast<size_t>(di.lds_per_block)) continue;
-        const int maxb = blocks_per_cu(p->D, p->R, blk, p->ncol_max, di, 0, maxthr);
-        for (int bpc = 1; bpc <= maxb; bpc *= 2) cands.push_back({blk, bpc});
-        if (maxb & (maxb - 1)) cands.push_back({blk, maxb});
+    for (int px : {kPxPerLane, kPxWide}) {
+        if (px == kPxWide && !p->wide_ok) continue;
+        const int wi = px == kPxWide ? 1 : 0;
+        const int maxthr = apply_max_block(p->io, wi ? true : p->fast_map != 0, false, px);
+        for (int blk : {64, 128, 256, 512, 1024}) {
+            if (blk > maxthr) continue;
+            if (apply_lds_bytes(p->D, p->R, blk, p->ncol_w[wi]) > static_cast<size_t>(di.lds_per_block)) continue;
+            const int maxb = blocks_per_cu(p->D, p->R, blk, p->ncol_w[wi], di, 0, maxthr);
+            for (int bpc = 1; bpc <= maxb; bpc *= 2) cands.push_back({blk, bpc, px});
+            if (maxb & (maxb - 1)) cands.push_back({blk, maxb, px});
+        }
     }
     if (cands.empty()) return fail(SVDLUT_EUNSUPPORTED, "plan_autotune: no candidate fits LDS");
     hipEvent_t e0, e1;
@@ -693,7 +738,7 @@ svdlut_status svdlut_plan_autotune(svdlut_plan* p, const void* x, void* y, const
     float best = 1e30f;
     Cand bestc = cands[0];
     for (const Cand& c : cands) {
-        plan_set_shape(p, c.block, c.bpc, di);
+        plan_set_shape(p, c.block, c.bpc, c.px, di);
         const ApplyLaunch a = plan_args(p, x, y, U, s, V, map, bias);
         svdlut_status st = launch_apply(a, stream);   // warm-up
         if (st != SVDLUT_OK) { (void)hipEventDestroy(e0); (void)hipEventDestroy(e1); return st; }
@@ -711,15 +756,29 @@ svdlut_status svdlut_plan_autotune(svdlut_plan* p, const void* x, void* y, const
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    plan_set_shape(p, bestc.block, bestc.bpc, di);
+    plan_set_shape(p, bestc.block, bestc.bpc, bestc.px, di);
     p->tuned = 1;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
-        g_tune[tune_key(p, di)] = TuneEntry{bestc.block, bestc.bpc};
+        g_tune[tune_key(p, di)] = TuneEntry{bestc.block, bestc.bpc, bestc.px};
         tune_save_locked();
     }
     plan_drop_graph(p);
+    return SVDLUT_OK;
+}
+
+svdlut_status svdlut_plan_set_shape(svdlut_plan* p, int32_t block, int32_t blocks_per_cu, int32_t px_per_lane) {
+    if (!p) return fail(SVDLUT_EINVAL, "plan_set_shape: null plan");
+    if (px_per_lane != kPxPerLane && px_per_lane != kPxWide)
+        return fail(SVDLUT_EINVAL, "plan_set_shape: px_per_lane must be 4 or 8");
+    if (!tune_entry_ok(TuneEntry{block, blocks_per_cu, px_per_lane}))
+        return fail(SVDLUT_EINVAL, "plan_set_shape: block must be 64, 128, 256, 512 or 1024 and blocks_per_cu in [1, 32]");
+    const DeviceInfo& di = device_info();
+    if (!plan_shape_ok(p, block, blocks_per_cu, px_per_lane, di))
+        return fail(SVDLUT_EUNSUPPORTED, "plan_set_shape: shape not supported for this batch (workgroup size, "
+                                         "workgroups per CU or LDS, or 8 pixels per lane with a map too fine)");
+    plan_set_shape(p, block, blocks_per_cu, px_per_lane, di);
     return SVDLUT_OK;
 }
 
@@ -731,8 +790,8 @@ svdlut_status svdlut_plan_get_info(const svdlut_plan* p, svdlut_plan_info* info)
     info->grid = p->grid;
     info->tuned = p->tuned;
     info->graph = p->have_graph ? 1 : 0;
-    info->tile_px = kSeg;
-    info->px_per_lane = kPxPerLane;
+    info->tile_px = kWave * p->px;
+    info->px_per_lane = p->px;
     info->blocks_per_cu = p->bpc;
     info->reserved = 0;
     return SVDLUT_OK;
@@ -742,7 +801,8 @@ svdlut_status svdlut_plan_destroy(svdlut_plan* p) {
     if (!p) return SVDLUT_OK;
     plan_drop_graph(p);
     if (p->d_descs) (void)hipFree(p->d_descs);
-    if (p->d_tiles) (void)hipFree(p->d_tiles);
+    if (p->d_tiles[0]) (void)hipFree(p->d_tiles[0]);
+    if (p->d_tiles[1]) (void)hipFree(p->d_tiles[1]);
     delete p;
     return SVDLUT_OK;
 }

@@ -18,6 +18,9 @@ constexpr int kMaxGenBatch = 4096;   // images per generator call (keeps its int
 constexpr int kWave = 64;
 constexpr int kPxPerLane = 4;                      // pixels per lane per row segment
 constexpr int kSeg = kWave * kPxPerLane;           // pixels per row segment (one wave)
+// The uneven-batch plan may also run 8 pixels per lane (512-pixel segments) when every map
+// is coarse enough for the piecewise map path at that width and there are no grids.
+constexpr int kPxWide = 8;
 
 void set_error(const std::string& msg);
 svdlut_status fail(svdlut_status st, const std::string& msg);
@@ -54,7 +57,8 @@ struct ApplyLaunch {
     const int64_t* tile_start;     // device [B+1] prefix of row segments, uneven batch only
     int64_t total_tiles;
     int32_t ncol_max;              // staged map columns per wave
-    int32_t fast_map;              // 1: map at most 1/3 of image resolution (piecewise path)
+    int32_t fast_map;              // 1: a lane's pixels lie within two map cells (piecewise path)
+    int32_t px;                    // pixels per lane: 4 (0 reads as 4) or kPxWide (plan only)
     int32_t block;                 // threads per workgroup
     int32_t grid;                  // workgroups
     svdlut_dtype io, map_dt;
@@ -72,9 +76,9 @@ __host__ __device__ inline int grid_plane_stride(int Ds) { return Ds | 1; }
 __host__ __device__ inline int grid_floats(int Ds) { return 9 * Ds * grid_plane_stride(Ds); }
 
 size_t apply_lds_bytes(int D, int R, int block, int ncol_max, int Ds = 0);
-int apply_max_block(svdlut_dtype io, bool fast_map, bool grid);
-int map_cols_bound(int W, int w);
-bool map_fast_ok(int W, int w);
+int apply_max_block(svdlut_dtype io, bool fast_map, bool grid, int px = kPxPerLane);
+int map_cols_bound(int W, int w, int px = kPxPerLane);
+bool map_fast_ok(int W, int w, int px = kPxPerLane);
 svdlut_status launch_apply(const ApplyLaunch& a, hipStream_t st);
 svdlut_status launch_reconstruct(const float* U, const float* s, const float* V, float* T,
                                  int n, int D, int R, hipStream_t st);

@@ -41,18 +41,19 @@ svdlut_status launch_reconstruct(const float* U, const float* s, const float* V,
 }
 
 // ---------------------------------------------------------------- fused apply
-// Work unit ("tile"): one row segment of kSeg = 256 pixels of one image, processed by one
-// wave (4 consecutive pixels per lane).  Tiles are numbered image-major, row-major.  Each
+// Work unit ("tile"): one row segment of 64 * PX pixels of one image, processed by one wave
+// (PX consecutive pixels per lane; PX = 4, 256-pixel segments, except in an uneven-batch plan
+// tuned to PX = 8).  Tiles are numbered image-major, row-major.  Each
 // workgroup takes a contiguous chunk of tiles; within each image the chunk is split into
 // contiguous per-wave runs.  Before the first tile of an image the workgroup rebuilds that
 // image's LUTs into LDS.
 //
 // Spatial map: per tile the wave stages, for every map column the segment touches, the
 // nine map channels blended between the two map rows around the tile's row
-// (r_l(col) = (1-dv) m_l[iv][col] + dv m_l[iv+1][col]).  When the map has at most a third
-// of the image's resolution (FASTMAP) a lane's 4 pixels lie within staged columns
-// c0..c0+2 and S_l = r0 + a*(r1-r0) + b*(r2-r1) with a = min(t, 1), b = max(t-1, 0),
-// t = u - c0; otherwise each pixel blends its own pair of columns.
+// (r_l(col) = (1-dv) m_l[iv][col] + dv m_l[iv+1][col]).  When the map is coarse enough that a
+// lane's PX pixels lie within staged columns c0..c0+2 (FASTMAP: (PX-1)(w-1) <= W-1),
+// S_l = r0 + a*(r1-r0) + b*(r2-r1) with a = min(t, 1), b = max(t-1, 0), t = u - c0; otherwise
+// each pixel blends its own pair of columns.
 
 struct Geo {
     int H, W, h, w;
@@ -63,7 +64,9 @@ struct Geo {
     AxisMap ax, ay;  // map coordinates along x (W -> w) and y (H -> h)
 };
 
+template <int PX>
 __device__ __forceinline__ Geo image_geo(const ApplyLaunch& a, int b, int io_bytes) {
+    constexpr int SEG = kWave * PX;
     Geo g;
     if (a.descs) {
         const ImgGeom d = a.descs[b];
@@ -76,11 +79,13 @@ __device__ __forceinline__ Geo image_geo(const ApplyLaunch& a, int b, int io_byt
         g.x_off = static_cast<int64_t>(b) * 3 * plane;
         g.y_off = g.x_off;
         g.map_off = static_cast<int64_t>(b) * 9 * a.h * a.w;
-        g.tile0 = static_cast<int64_t>(b) * a.H * ((a.W + kSeg - 1) / kSeg);
+        g.tile0 = static_cast<int64_t>(b) * a.H * ((a.W + SEG - 1) / SEG);
     }
-    g.nseg = (g.W + kSeg - 1) / kSeg;
+    g.nseg = (g.W + SEG - 1) / SEG;
     const int64_t plane = static_cast<int64_t>(g.H) * g.W;
-    g.vec_ok = ((g.x_off | g.y_off | plane | g.W) & 3) == 0 &&
+    // VEC lanes past the row end take the row's last PX pixels, which must lie in the row's
+    // last segment: rows of at least PX pixels whose last segment holds at least PX of them
+    g.vec_ok = ((g.x_off | g.y_off | plane | g.W) & 3) == 0 && g.W >= PX && (g.W % SEG == 0 || g.W % SEG >= PX) &&
                ((reinterpret_cast<uintptr_t>(a.x) | reinterpret_cast<uintptr_t>(a.y)) &
                 (4 * static_cast<uintptr_t>(io_bytes) - 1)) == 0;
     g.ax = make_axis(g.W, g.w);
@@ -88,9 +93,10 @@ __device__ __forceinline__ Geo image_geo(const ApplyLaunch& a, int b, int io_byt
     return g;
 }
 
+template <int PX>
 __device__ __forceinline__ int image_of_tile(const ApplyLaunch& a, int64_t t) {
     if (!a.descs) {
-        const int64_t per = static_cast<int64_t>(a.H) * ((a.W + kSeg - 1) / kSeg);
+        const int64_t per = static_cast<int64_t>(a.H) * ((a.W + kWave * PX - 1) / (kWave * PX));
         return static_cast<int>(t / per);
     }
     int lo = 0, hi = a.B - 1;            // largest b with tile_start[b] <= t
@@ -101,22 +107,30 @@ __device__ __forceinline__ int image_of_tile(const ApplyLaunch& a, int64_t t) {
     return lo;
 }
 
-// Pixels of the lane for the tile at row y, segment start xs: 3 channels x 4 pixels.  VEC
-// (rows 4-element aligned): one vector load per channel, lanes past the row end re-read
-// the row's last four pixels; otherwise element loads with the index clamped to the row.
-template <typename IO, bool VEC>
-__device__ __forceinline__ void load_tile(const ApplyLaunch& a, const Geo& g, int y, int xs, float (&px)[3][4]) {
+// Pixels of the lane for the tile at row y, segment start xs: 3 channels x PX pixels.  VEC
+// (rows 4-element aligned, at least PX long): 4-element vector loads, lanes past the row end
+// re-read the row's last PX pixels; otherwise element loads with the index clamped to the row.
+template <typename IO, bool VEC, int PX>
+__device__ __forceinline__ void load_tile(const ApplyLaunch& a, const Geo& g, int y, int xs, float (&px)[3][PX]) {
     const int lane = threadIdx.x & (kWave - 1);
-    const int x0 = min(xs + lane * kPxPerLane, VEC ? g.W - kPxPerLane : g.W - 1);
+    const int x0 = min(xs + lane * PX, VEC ? g.W - PX : g.W - 1);
     const int64_t plane = static_cast<int64_t>(g.H) * g.W;
     const IO* xin = reinterpret_cast<const IO*>(a.x) + g.x_off + static_cast<int64_t>(y) * g.W;
 #pragma unroll
-    for (int c = 0; c < 3; ++c) load_px4<IO, VEC>(xin + c * plane, x0, g.W, px[c]);
+    for (int c = 0; c < 3; ++c)
+#pragma unroll
+        for (int q = 0; q < PX / 4; ++q) {
+            float t[4];
+            load_px4<IO, VEC>(xin + c * plane, x0 + 4 * q, g.W, t);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) px[c][4 * q + e] = t[e];
+        }
 }
 
 // Map columns of the segment starting at xs: first staged column and count.
+template <int PX>
 __device__ __forceinline__ void seg_columns(const Geo& g, int xs, int& clo, int& ncols) {
-    const int xlast = min(xs + kSeg, g.W) - 1;
+    const int xlast = min(xs + kWave * PX, g.W) - 1;
     int chi; uint32_t r;
     axis_left(g.ax, xs, clo, r);
     axis_left(g.ax, xlast, chi, r);
@@ -213,15 +227,15 @@ struct GridTile {
     int Ds, Dsp;
 };
 
-template <typename IO, bool FASTMAP, bool VEC, bool GRID, bool VST>
+template <typename IO, bool FASTMAP, bool VEC, bool GRID, bool VST, int PX>
 __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g, const float* Tl,
                                              const float* stage, int clo, int D, int y, int xs,
-                                             const float (&px)[3][4], const float (&bias3)[3],
+                                             const float (&px)[3][PX], const float (&bias3)[3],
                                              const GridTile& gt) {
     // Lanes past the row end work on the row's last pixels (the same x0 as load_tile) and
     // store the same values again, so every lane issues the same loads and stores.
     const int lane = threadIdx.x & (kWave - 1);
-    const int x0 = min(xs + lane * kPxPerLane, VEC ? g.W - kPxPerLane : g.W - 1);
+    const int x0 = min(xs + lane * PX, VEC ? g.W - PX : g.W - 1);
     int c0; uint32_t rem0;
     axis_left(g.ax, x0, c0, rem0);
     const float Dm1 = static_cast<float>(D - 1);
@@ -231,7 +245,7 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
     const float RS4 = static_cast<float>(4 * RS), PS4 = static_cast<float>(4 * PS);
     const float Dm2f = static_cast<float>(Dm2);
     (void)PS;
-    float out[3][4];
+    float out[3][PX];
     float r0[9], d01[9], d12[9];
     if (FASTMAP) {
         const float* s0 = stage + (c0 - clo) * Stg<VST>::map;
@@ -245,7 +259,7 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
     }
     const uint32_t den = g.ax.div.d;
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
+    for (int k = 0; k < PX; ++k) {
         float S[9];
         if (FASTMAP) {
             const uint32_t n = rem0 + static_cast<uint32_t>(k) * g.ax.num_step;
@@ -342,24 +356,40 @@ __device__ __forceinline__ void compute_tile(const ApplyLaunch& a, const Geo& g,
     }
     const int64_t plane = static_cast<int64_t>(g.H) * g.W;
     IO* yout = reinterpret_cast<IO*>(a.y) + g.y_off + static_cast<int64_t>(y) * g.W;
-    store_px4<IO, VEC>(yout, x0, g.W, out[0]);
-    store_px4<IO, VEC>(yout + plane, x0, g.W, out[1]);
-    store_px4<IO, VEC>(yout + 2 * plane, x0, g.W, out[2]);
+    if constexpr (PX == 4) {
+        store_px4<IO, VEC>(yout, x0, g.W, out[0]);
+        store_px4<IO, VEC>(yout + plane, x0, g.W, out[1]);
+        store_px4<IO, VEC>(yout + 2 * plane, x0, g.W, out[2]);
+    } else {
+        // per group of four: without VEC a group that starts past the row end holds only
+        // pixels beyond it (the first group's stores cover the row's last pixel) and is skipped
+#pragma unroll
+        for (int q = 0; q < PX / 4; ++q) {
+            if (!VEC && x0 + 4 * q > g.W - 1) continue;
+#pragma unroll
+            for (int c = 0; c < 3; ++c) {
+                float t[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) t[e] = out[c][4 * q + e];
+                store_px4<IO, VEC>(yout + c * plane, x0 + 4 * q, g.W, t);
+            }
+        }
+    }
 }
 
 // Largest workgroup an instantiation is compiled for.  Half-precision I/O with grid slicing
 // or with per-pixel map columns needs more than the 128 VGPRs per lane that a 1024-thread
 // workgroup leaves (it spilled to scratch and ran 4-5x slower), so those variants are built
-// for 512 threads (up to 256 VGPRs, 8 waves per CU).
-template <typename IO, bool FASTMAP, bool GRID>
-constexpr int apply_threads() { return (sizeof(IO) == 2 && (GRID || !FASTMAP)) ? 512 : 1024; }
+// for 512 threads (up to 256 VGPRs, 8 waves per CU), as are the 8-pixel-per-lane ones.
+template <typename IO, bool FASTMAP, bool GRID, int PX = kPxPerLane>
+constexpr int apply_threads() { return (PX > kPxPerLane || (sizeof(IO) == 2 && (GRID || !FASTMAP))) ? 512 : 1024; }
 
 // One image's share [ta, tb) (local row-major tile indices) of a workgroup's chunk.  Inside
 // it the tiles are walked column-major (same segment, consecutive rows) in one contiguous
 // run per wave, so a wave keeps its staged raw map rows for about h/H of a map cell's
 // height in pixel rows and only re-reads the map when the segment or the pair of map rows
 // changes.  VEC is uniform per image, so the hot loop has a single load/store form.
-template <typename IO, typename MT, bool FASTMAP, bool VEC, bool GRID, bool VST>
+template <typename IO, typename MT, bool FASTMAP, bool VEC, bool GRID, bool VST, int PX>
 __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, int b, int ta, int tb,
                                           int wave, int nw, float* Tl, float* Gl, float* aux, float* stage,
                                           float* raw) {
@@ -410,9 +440,10 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
     // before the LUT rebuild, so their memory latency overlaps it, and each later tile's right
     // after the previous tile.  The 512-thread variants measured faster loading each tile's
     // pixels at its start.
-    constexpr bool EARLY = apply_threads<IO, FASTMAP, GRID>() == 1024;
-    float px[3][4];
-    if (EARLY && k < k1) load_tile<IO, VEC>(a, g, ya + yr, seg * kSeg, px);
+    constexpr bool EARLY = apply_threads<IO, FASTMAP, GRID, PX>() == 1024;
+    constexpr int SEG = kWave * PX;
+    float px[3][PX];
+    if (EARLY && k < k1) load_tile<IO, VEC, PX>(a, g, ya + yr, seg * SEG, px);
     const size_t foff = static_cast<size_t>(b) * 9 * D * a.R;
     stage_luts(Tl, aux, a.U + foff, a.s + static_cast<size_t>(b) * 9 * a.R, a.V + foff, D, a.R, min(a.R, 8));
     float bias3[3] = {0.f, 0.f, 0.f};
@@ -430,12 +461,12 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
     int st_seg = -1, st_iv = -1, clo = 0, ncols = 0;
     while (k < k1) {
         const int y = ya + yr;
-        const int xs = seg * kSeg;
-        if (!EARLY) load_tile<IO, VEC>(a, g, y, xs, px);
+        const int xs = seg * SEG;
+        if (!EARLY) load_tile<IO, VEC, PX>(a, g, y, xs, px);
         int iv; uint32_t remv;
         axis_left(g.ay, y, iv, remv);
         if (seg != st_seg || iv != st_iv) {
-            seg_columns(g, xs, clo, ncols);
+            seg_columns<PX>(g, xs, clo, ncols);
             stage_raw<MT, VST>(a, g, iv, clo, ncols, raw);
             st_seg = seg;
             st_iv = iv;
@@ -448,20 +479,20 @@ __device__ __forceinline__ void run_image(const ApplyLaunch& a, const Geo& g, in
             axis_left(gay, y, gt.iy, ry);
             gt.dy = static_cast<float>(ry) * gay.inv;
         }
-        compute_tile<IO, FASTMAP, VEC, GRID, VST>(a, g, Tl, stage, clo, D, y, xs, px, bias3, gt);
+        compute_tile<IO, FASTMAP, VEC, GRID, VST, PX>(a, g, Tl, stage, clo, D, y, xs, px, bias3, gt);
         wave_sync();   // the stage region is rewritten for the next tile
         advance(seg, yr, k);
-        if (EARLY && k < k1) load_tile<IO, VEC>(a, g, ya + yr, seg * kSeg, px);
+        if (EARLY && k < k1) load_tile<IO, VEC, PX>(a, g, ya + yr, seg * SEG, px);
     }
 }
 
-int apply_max_block(svdlut_dtype io, bool fast_map, bool grid) {
-    return (io == SVDLUT_F16 && (grid || !fast_map)) ? 512 : 1024;
+int apply_max_block(svdlut_dtype io, bool fast_map, bool grid, int px) {
+    return (px > kPxPerLane || (io == SVDLUT_F16 && (grid || !fast_map))) ? 512 : 1024;
 }
 
 // Persistent kernel: workgroup chunk -> per-image sub-ranges -> per-wave runs.
-template <typename IO, typename MT, bool FASTMAP, bool GRID, bool VST>
-__global__ void __launch_bounds__((apply_threads<IO, FASTMAP, GRID>())) apply_kernel(ApplyLaunch a) {
+template <typename IO, typename MT, bool FASTMAP, bool GRID, bool VST, int PX = kPxPerLane>
+__global__ void __launch_bounds__((apply_threads<IO, FASTMAP, GRID, PX>())) apply_kernel(ApplyLaunch a) {
     extern __shared__ float smem[];
     const int D = a.D;
     float* Tl = smem;
@@ -480,31 +511,32 @@ __global__ void __launch_bounds__((apply_threads<IO, FASTMAP, GRID>())) apply_ke
     int64_t t0 = static_cast<int64_t>(lb) * per;
     const int64_t t1 = min(a.total_tiles, t0 + per);
     while (t0 < t1) {
-        const int b = image_of_tile(a, t0);
-        const Geo g = image_geo(a, b, sizeof(IO));
+        const int b = image_of_tile<PX>(a, t0);
+        const Geo g = image_geo<PX>(a, b, sizeof(IO));
         const int64_t img_end = g.tile0 + static_cast<int64_t>(g.H) * g.nseg;
         const int64_t te = min(t1, img_end);
         const int ta = static_cast<int>(t0 - g.tile0);
         const int tb = static_cast<int>(te - g.tile0);
         if (g.vec_ok)
-            run_image<IO, MT, FASTMAP, true, GRID, VST>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
+            run_image<IO, MT, FASTMAP, true, GRID, VST, PX>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
         else
-            run_image<IO, MT, FASTMAP, false, GRID, VST>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
+            run_image<IO, MT, FASTMAP, false, GRID, VST, PX>(a, g, b, ta, tb, wave, nw, Tl, Gl, aux, stage, raw);
         t0 = te;
         __syncthreads();   // every wave is done with Tl and aux before the next image
     }
 }
 
-int map_cols_bound(int W, int w) {
-    // columns touched by one segment: c0(last) - c0(first) <= floor(255*(w-1)/(W-1)) + 1, plus 2
+int map_cols_bound(int W, int w, int px) {
+    // columns touched by one segment of n = 64 px pixels:
+    // c0(last) - c0(first) <= floor((n-1)*(w-1)/(W-1)) + 1, plus 2
     if (w <= 1) return 1;
-    const int64_t span = (W > 1) ? (static_cast<int64_t>(kSeg - 1) * (w - 1)) / (W - 1) : 0;
+    const int64_t span = (W > 1) ? (static_cast<int64_t>(kWave * px - 1) * (w - 1)) / (W - 1) : 0;
     return static_cast<int>(std::min<int64_t>(w, span + 4));
 }
 
-bool map_fast_ok(int W, int w) {
-    // a lane's 4 pixels must lie within two map cells: 3*(w-1) <= W-1
-    return static_cast<int64_t>(3) * (w - 1) <= static_cast<int64_t>(W - 1);
+bool map_fast_ok(int W, int w, int px) {
+    // a lane's px pixels must lie within two map cells: (px-1)*(w-1) <= W-1
+    return static_cast<int64_t>(px - 1) * (w - 1) <= static_cast<int64_t>(W - 1);
 }
 
 size_t apply_lds_bytes(int D, int R, int block, int ncol_max, int Ds) {
@@ -517,17 +549,19 @@ size_t apply_lds_bytes(int D, int R, int block, int ncol_max, int Ds) {
     return sizeof(float) * (lut + grid + std::max(scratch, stage));
 }
 
-template <typename IO, typename MT, bool FASTMAP, bool GRID>
+template <typename IO, typename MT, bool FASTMAP, bool GRID, int PX = kPxPerLane>
 static void launch_staged(const ApplyLaunch& a, size_t lds, hipStream_t st) {
     if (vec_stage(a.ncol_max))
-        hipLaunchKernelGGL((apply_kernel<IO, MT, FASTMAP, GRID, true>), dim3(a.grid), dim3(a.block), lds, st, a);
+        hipLaunchKernelGGL((apply_kernel<IO, MT, FASTMAP, GRID, true, PX>), dim3(a.grid), dim3(a.block), lds, st, a);
     else
-        hipLaunchKernelGGL((apply_kernel<IO, MT, FASTMAP, GRID, false>), dim3(a.grid), dim3(a.block), lds, st, a);
+        hipLaunchKernelGGL((apply_kernel<IO, MT, FASTMAP, GRID, false, PX>), dim3(a.grid), dim3(a.block), lds, st, a);
 }
 
 template <typename IO, typename MT>
 static void launch_typed(const ApplyLaunch& a, size_t lds, hipStream_t st) {
-    if (a.K > 0) {
+    if (a.px == kPxWide) {   // validated by launch_apply: piecewise map path, no grids
+        launch_staged<IO, MT, true, false, kPxWide>(a, lds, st);
+    } else if (a.K > 0) {
         if (a.fast_map) launch_staged<IO, MT, true, true>(a, lds, st);
         else launch_staged<IO, MT, false, true>(a, lds, st);
     } else {
@@ -537,7 +571,12 @@ static void launch_typed(const ApplyLaunch& a, size_t lds, hipStream_t st) {
 }
 
 svdlut_status launch_apply(const ApplyLaunch& a, hipStream_t st) {
-    if (a.block > apply_max_block(static_cast<svdlut_dtype>(a.io), a.fast_map != 0, a.K > 0))
+    if (a.px != 0 && a.px != kPxPerLane && a.px != kPxWide)
+        return fail(SVDLUT_EINVAL, "apply: pixels per lane must be 4 or 8");
+    if (a.px == kPxWide && (!a.fast_map || a.K > 0))
+        return fail(SVDLUT_EINVAL, "apply: 8 pixels per lane need the piecewise map path and no grids");
+    if (a.block > apply_max_block(static_cast<svdlut_dtype>(a.io), a.fast_map != 0, a.K > 0,
+                                  a.px == kPxWide ? kPxWide : kPxPerLane))
         return fail(SVDLUT_EINVAL, "apply: workgroup larger than the kernel variant allows");
     const size_t lds = apply_lds_bytes(a.D, a.R, a.block, a.ncol_max, a.K > 0 ? a.Ds : 0);
     if (a.io == SVDLUT_F32) {

@@ -1,6 +1,7 @@
-// Tuning cache of the uneven-batch plan: a flat JSON object {"key": [block, blocks_per_cu], ...}
-// mapping a problem class to the fastest workgroup shape found for it.  Host code only (no
-// HIP), so that a CPU build can exercise the parser on its own.
+// Tuning cache of the uneven-batch plan: a flat JSON object
+// {"key": [block, blocks_per_cu, px_per_lane], ...} mapping a problem class to the fastest
+// launch shape found for it (an entry without the third value means 4 pixels per lane).
+// Host code only (no HIP), so that a CPU build can exercise the parser on its own.
 #pragma once
 
 #include <cctype>
@@ -11,13 +12,14 @@
 namespace svdlut {
 
 struct TuneEntry {
-    int block;   // threads per workgroup: 64, 128, 256, 512 or 1024
-    int bpc;     // workgroups per CU in the persistent launch: 1 .. 32
+    int block;    // threads per workgroup: 64, 128, 256, 512 or 1024
+    int bpc;      // workgroups per CU in the persistent launch: 1 .. 32
+    int px = 4;   // pixels per lane (tile width 64 * px): 4 or 8
 };
 
 inline bool tune_entry_ok(const TuneEntry& e) {
     return (e.block == 64 || e.block == 128 || e.block == 256 || e.block == 512 || e.block == 1024) && e.bpc >= 1 &&
-           e.bpc <= 32;
+           e.bpc <= 32 && (e.px == 4 || e.px == 8);
 }
 
 namespace tune_detail {
@@ -62,7 +64,7 @@ inline int parse_tune_cache(const std::string& txt, std::map<std::string, TuneEn
         skip_ws(txt, i);
         if (i >= txt.size() || txt[i] != '[') continue;
         ++i;
-        TuneEntry e{0, 0};
+        TuneEntry e{0, 0, 4};
         skip_ws(txt, i);
         if (!read_int(txt, i, e.block)) continue;
         skip_ws(txt, i);
@@ -71,6 +73,12 @@ inline int parse_tune_cache(const std::string& txt, std::map<std::string, TuneEn
         skip_ws(txt, i);
         if (!read_int(txt, i, e.bpc)) continue;
         skip_ws(txt, i);
+        if (i < txt.size() && txt[i] == ',') {   // optional third value: pixels per lane
+            ++i;
+            skip_ws(txt, i);
+            if (!read_int(txt, i, e.px)) continue;
+            skip_ws(txt, i);
+        }
         if (i >= txt.size() || txt[i] != ']') continue;
         pos = i + 1;
         if (!tune_entry_ok(e) || k1 - k0 - 1 > 512) continue;
@@ -85,7 +93,7 @@ inline std::string format_tune_cache(const std::map<std::string, TuneEntry>& m) 
     size_t i = 0;
     for (const auto& kv : m) {
         s += "  \"" + kv.first + "\": [" + std::to_string(kv.second.block) + ", " + std::to_string(kv.second.bpc) +
-             "]" + (++i < m.size() ? "," : "") + "\n";
+             ", " + std::to_string(kv.second.px) + "]" + (++i < m.size() ? "," : "") + "\n";
     }
     s += "}\n";
     return s;

@@ -62,6 +62,11 @@ class Plan:
     def autotune(self, x, y, U, s, V, smap, bias=None):
         check(_lib.load().svdlut_plan_autotune(*self._args(x, y, U, s, V, smap, bias)), "svdlut_plan_autotune")
 
+    def set_shape(self, block, blocks_per_cu, px_per_lane=4):
+        """Launch shape by hand: threads per workgroup, workgroups per CU, pixels per lane (4 or 8)."""
+        check(_lib.load().svdlut_plan_set_shape(self._h, int(block), int(blocks_per_cu), int(px_per_lane)),
+              "svdlut_plan_set_shape")
+
     def info(self):
         inf = PlanInfo()
         check(_lib.load().svdlut_plan_get_info(self._h, C.byref(inf)), "svdlut_plan_get_info")

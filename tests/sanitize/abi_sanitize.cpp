@@ -90,6 +90,7 @@ static void validation() {
     svdlut_plan* plan = nullptr;
     refused(svdlut_plan_create(nullptr, 1, 33, 8, F32, F32, &plan), nullptr);
     refused(svdlut_plan_launch(nullptr, f, f, cf, cf, cf, f, nullptr, nullptr), nullptr);
+    refused(svdlut_plan_set_shape(nullptr, 512, 1, 4), nullptr);
     CHECK(svdlut_plan_destroy(nullptr) == SVDLUT_OK);
     refused(svdlut_generator_fwd(nullptr, f, F32, 1, 256, 256, 33, 8, ff, ff, ff, ff, f, 1u << 30, nullptr), nullptr);
     refused(svdlut_generator_fwd(cf, f, F32, 1, 256, 256, 33, 8, ff, ff, ff, ff, f, 16, nullptr), nullptr);
@@ -136,11 +137,14 @@ static void tune_cache() {
     using svdlut::TuneEntry;
     std::map<std::string, TuneEntry> m;
     CHECK(svdlut::parse_tune_cache("{\n  \"gfx950|a\": [512, 2],\n  \"gfx950|b\": [1024,1]\n}\n", m) == 2);
-    CHECK(m["gfx950|a"].block == 512 && m["gfx950|a"].bpc == 2);
+    CHECK(m["gfx950|a"].block == 512 && m["gfx950|a"].bpc == 2 && m["gfx950|a"].px == 4);
+    // the third value: pixels per lane
+    CHECK(svdlut::parse_tune_cache("{\"gfx950|c\": [256, 4, 8]}", m) == 1);
+    CHECK(m["gfx950|c"].block == 256 && m["gfx950|c"].bpc == 4 && m["gfx950|c"].px == 8);
     // round trip
     std::map<std::string, TuneEntry> m2;
-    CHECK(svdlut::parse_tune_cache(svdlut::format_tune_cache(m), m2) == 2);
-    CHECK(m2.size() == 2 && m2["gfx950|b"].block == 1024);
+    CHECK(svdlut::parse_tune_cache(svdlut::format_tune_cache(m), m2) == 3);
+    CHECK(m2.size() == 3 && m2["gfx950|b"].block == 1024 && m2["gfx950|c"].px == 8 && m2["gfx950|a"].px == 4);
     const char* bad[] = {"",
                          "{",
                          "\"",
@@ -161,6 +165,10 @@ static void tune_cache() {
                          "[512, 2]",
                          "\"k\" [512, 2]",
                          "{\"k\": [512 2]}",
+                         "{\"k\": [512, 2, 6]}",
+                         "{\"k\": [512, 2, 8, 1]}",
+                         "{\"k\": [512, 2,]}",
+                         "{\"k\": [512, 2, \"8\"]}",
                          "\xff\xfe\x00\x01"};
     for (const char* b : bad) {
         std::map<std::string, TuneEntry> mb;

@@ -109,6 +109,7 @@ def test_validation_happens_before_any_hip_call(lib):
     out = C.c_void_p()
     assert lib.svdlut_plan_create(null, 1, 33, 8, 1, 1, C.byref(out)) == 1
     assert lib.svdlut_plan_launch(null, fake, fake, fake, fake, fake, fake, null, null) == 1
+    assert lib.svdlut_plan_set_shape(null, 512, 1, 4) == 1
     assert lib.svdlut_plan_destroy(null) == 0
     # generator
     assert lib.svdlut_generator_fwd(null, fake, 0, 1, 256, 256, 33, 8, fake, fake, fake, fake, fake, 1 << 30, null) == 1

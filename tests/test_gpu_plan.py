@@ -205,7 +205,8 @@ def test_plan_fallbacks_and_tuning_cache(tmp_path):
     shape and autotune writes a valid one; a later process takes its shape from that file
     without tuning; a corrupt file, or an entry with values out of range, is ignored (the
     default shape, the same output) and autotune replaces it with valid JSON.  The output is
-    the same bit for bit in every case: no pixel's arithmetic depends on the launch shape."""
+    the same bit for bit in every case with 4 pixels per lane (the workgroup shape changes no
+    pixel's arithmetic); a tuned 8-pixel tile agrees to rounding."""
     import json
     base, y_ref = _child(tmp_path, "graph", {})
     assert base["before"]["graph"] == 1 or base["after"]["graph"] == 1
@@ -219,19 +220,36 @@ def test_plan_fallbacks_and_tuning_cache(tmp_path):
     miss, y = _child(tmp_path, "missing", {"SVDLUT_TUNE_CACHE": str(cache)}, autotune=True)
     assert miss["before"]["tuned"] == 0 and miss["after"]["tuned"] == 1
     assert miss["before"]["block"] == base["before"]["block"]
+    assert (base["before"]["px_per_lane"], base["before"]["tile_px"]) == (4, 256)
     entries = json.load(open(cache))
     assert len(entries) == 1
-    key, (blk, bpc) = next(iter(entries.items()))
-    assert blk in (64, 128, 256, 512, 1024) and 1 <= bpc <= 32
-    # every pixel's arithmetic is independent of the launch shape: same output bit for bit
-    np.testing.assert_array_equal(y, y_ref)
+    key, (blk, bpc, px) = next(iter(entries.items()))
+    assert blk in (64, 128, 256, 512, 1024) and 1 <= bpc <= 32 and px in (4, 8)
+    assert (miss["after"]["block"], miss["after"]["blocks_per_cu"], miss["after"]["px_per_lane"]) == (blk, bpc, px)
+    assert miss["after"]["tile_px"] == 64 * px
+
+    def same_output(y):
+        # 4 pixels per lane: bit for bit; 8: the map weights come from other staged columns
+        if px == 4:
+            np.testing.assert_array_equal(y, y_ref)
+        else:
+            np.testing.assert_allclose(y.astype(np.float32), y_ref.astype(np.float32), rtol=0, atol=2e-3)
+    same_output(y)
     # the cached shape is used by the next process without tuning
     hit, y = _child(tmp_path, "hit", {"SVDLUT_TUNE_CACHE": str(cache)})
     assert hit["before"]["tuned"] == 1 and hit["before"]["block"] == blk
+    assert hit["before"]["px_per_lane"] == px and hit["before"]["blocks_per_cu"] == bpc
     assert hit["direct_equal"]
+    same_output(y)
+    # an older two-value entry still reads as 4 pixels per lane
+    cache.write_text(json.dumps({key: [blk if blk <= 512 else 512, 1]}))
+    old, y = _child(tmp_path, "two_values", {"SVDLUT_TUNE_CACHE": str(cache)})
+    assert old["before"]["tuned"] == 1 and old["before"]["px_per_lane"] == 4
+    np.testing.assert_array_equal(y, y_ref)
     # corrupt files and out-of-range values are ignored
     for name, text in (("garbage", "\x00\xffnot json{{{["), ("truncated", '{"' + key + '": [51'),
-                       ("range", json.dumps({key: [999, 2]})), ("types", json.dumps({key: ["512", "x"]}))):
+                       ("range", json.dumps({key: [999, 2]})), ("types", json.dumps({key: ["512", "x"]})),
+                       ("px", json.dumps({key: [512, 1, 6]})), ("extra", json.dumps({key: [512, 1, 8, 1]}))):
         cache.write_bytes(text.encode("latin-1"))
         bad, y = _child(tmp_path, name, {"SVDLUT_TUNE_CACHE": str(cache)}, autotune=(name == "garbage"))
         assert bad["before"]["tuned"] == 0, name
@@ -265,3 +283,75 @@ def test_plan_degenerate_images(svd):
     assert torch.equal(y, y2)
     info = plan.info()
     assert info["pixels"] == sum(H * W for (H, W, _, _) in specs)
+
+
+# (H, W, h, w): rows of 4 and 516 pixels are 4-aligned, but their last 512-pixel segment holds
+# fewer than 8 pixels, so they take the element path
+WIDE_SPECS = [(1, 4, 1, 1), (3, 5, 2, 1), (9, 7, 3, 1), (16, 8, 2, 2), (5, 9, 2, 2), (17, 13, 3, 2),
+              (12, 100, 2, 13), (7, 511, 1, 64), (6, 513, 2, 65), (3, 516, 1, 65), (40, 1000, 5, 125),
+              (64, 256, 8, 32), (2, 1024, 1, 128)]
+
+
+def _images(specs, seed):
+    g = synth.rng(seed)
+    images = []
+    for (H, W, h, w) in specs:
+        x = synth.image(g, H, W)
+        U, s, V = synth.factors(g, 1, 33, 8)
+        m = synth.spatial_map(g, 1, h, w)
+        images.append((x, U[0], s[0], V[0], m[0]))
+    return synth.pack_uneven(images)
+
+
+@pytest.mark.parametrize("io,tol,agree", [(torch.float32, 1e-5, 2e-6), (torch.float16, 2e-3, 2e-3)])
+def test_plan_wide_tiles(svd, io, tol, agree):
+    """8 pixels per lane (512-pixel tiles), set by hand on a batch of ragged and short rows
+    (widths 4 to 1024, most not multiples of 8, 4-aligned rows shorter than 8) whose maps
+    allow it ((8-1)(w-1) <= W-1): every pixel against the oracle, the 4-pixel tiles to
+    rounding, the graph replay equal to the plain launch, and the info fields."""
+    packed = _images(WIDE_SPECS, 5150)
+    say(f"plan wide tiles {io}")
+    descs = packed[5]
+    assert all(7 * (d["w"] - 1) <= d["W"] - 1 for d in descs)
+    plan4 = svd.Plan(descs, 33, 8, io, io)
+    plan4.set_shape(512, 1, 4)
+    _, x, m, y4, (U, s, V) = run_plan(svd, packed, io, plan=plan4)
+    plan8 = svd.Plan(descs, 33, 8, io, io)
+    plan8.set_shape(512, 1, 8)
+    info = plan8.info()
+    assert (info["px_per_lane"], info["tile_px"], info["block"], info["blocks_per_cu"]) == (8, 512, 512, 1)
+    assert info["tiles"] == sum(d["H"] * -(-d["W"] // 512) for d in descs)
+    _, _, _, y8, _ = run_plan(svd, packed, io, plan=plan8)
+    assert plan8.info()["graph"] == 1
+    y8d = torch.zeros_like(y8)
+    plan8.launch_direct(x, y8d, U, s, V, m)
+    torch.cuda.synchronize()
+    assert torch.equal(y8, y8d)
+    oracle_check(packed, x, m, y8, tol)
+    assert (y8.float() - y4.float()).abs().max().item() <= agree
+    # back to 4 pixels per lane on the same plan: the graph is captured again, bit for bit
+    # what a 4-pixel plan gives
+    plan8.set_shape(512, 1, 4)
+    y44 = torch.zeros_like(y8)
+    plan8.launch(x, y44, U, s, V, m)
+    torch.cuda.synchronize()
+    assert torch.equal(y44, y4)
+
+
+def test_plan_set_shape_refusals(svd):
+    """Shapes a batch cannot run are refused and leave the plan as it was: values outside the
+    sets (EINVAL), 8 pixels per lane with a map too fine for it or with more than 512 threads,
+    and more workgroups per CU than the LDS holds (EUNSUPPORTED)."""
+    packed = _images([(20, 40, 20, 40), (8, 64, 1, 8)], 5160)     # the first map is per-pixel
+    plan = svd.Plan(packed[5], 33, 8, torch.float32, torch.float32)
+    before = plan.info()
+    for args, what in (((512, 1, 6), "px_per_lane"), ((500, 1, 4), "block"), ((512, 0, 4), "block"),
+                       ((512, 33, 4), "block"), ((256, 1, 8), "not supported"), ((512, 32, 4), "not supported")):
+        with pytest.raises(svd.SvdlutError, match=what):
+            plan.set_shape(*args)
+        assert plan.info() == before, args
+    coarse = svd.Plan(_images([(8, 64, 1, 8)], 5161)[5], 33, 8, torch.float32, torch.float32)
+    with pytest.raises(svd.SvdlutError, match="not supported"):
+        coarse.set_shape(1024, 1, 8)               # 8-pixel variants are built for 512 threads
+    coarse.set_shape(256, 2, 8)
+    assert coarse.info()["px_per_lane"] == 8
