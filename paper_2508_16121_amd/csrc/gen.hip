@@ -226,8 +226,8 @@ size_t carve_ws(char* base, int B, int D, int R, WS* w) {
     }
     if (w) w->skp = reinterpret_cast<float*>(base + off);
     off = align256(off + sizeof(float) * nsk);
-    size_t nwp = wgrad_part_floats(head_geo(B));
-    for (int i = 0; i < kConvs; ++i) nwp = std::max(nwp, wgrad_part_floats(conv_geo(i, B)));
+    size_t nwp = bwd_part_floats(head_geo(B));
+    for (int i = 0; i < kConvs; ++i) nwp = std::max(nwp, bwd_part_floats(conv_geo(i, B)));
     if (w) w->wpart = reinterpret_cast<float*>(base + off);
     off = align256(off + sizeof(float) * nwp);
     for (int i = 0; i <= kConvs; ++i) {

@@ -417,17 +417,34 @@ void gemm_nt(int ncols, AL al, BL bl, EP ep, int M, int K, int splitk, hipStream
     else gemm<4>(al, bl, ep, M, ncols, K, splitk, st);
 }
 
-// Split-K of a forward convolution: workgroups of a layer with few output pixels are too
-// few to hide the operand gathers, so its reduction is split into slices (at least two k
-// steps each) until about 256 workgroups run.  Each slice writes its partial product to
-// part[slice][m][n]; a second kernel sums the slices in fixed order and applies the bias and
-// the activation.  Returns the requested split (1 = no split) for an M x N x K product with
-// 16-column tiles.
+// Split-K.  A launch with few workgroups cannot hide its operand gathers, and each of its
+// waves walks the whole reduction.  An M x N x K product whose plain launch (gemm_nt's tile
+// width) has fewer than kNoSplitWgs workgroups and a reduction of at least 16 k steps is
+// split into slices of at least four k steps, run with 16-column tiles, until about
+// kSplitTarget workgroups run.  Each slice writes its partial product to part[slice][m][n];
+// a second kernel sums the slices in fixed order.  Returns the split (1 = none).
+constexpr int kNoSplitWgs = 512;
+constexpr int kSplitTarget = 1024;
+
+inline int gemm_nt_tiles(int ncols) { return ncols <= 16 ? 1 : (ncols <= 32 ? 2 : 4); }
+
+inline int long_k_splits(int M, int N, int K) {
+    const int ksteps = (K + 15) / 16;
+    const int wgs16 = ((M + 63) / 64) * ((N + 15) / 16);
+    const int nt = gemm_nt_tiles(N);
+    const int wgs_nt = ((M + 63) / 64) * ((N + 16 * nt - 1) / (16 * nt));
+    if (wgs_nt >= kNoSplitWgs || ksteps < 16) return 1;
+    return std::max(1, std::min(ksteps / 4, (kSplitTarget + wgs16 - 1) / wgs16));
+}
+
+// Forward convolutions: layers with very few output tiles (fewer than 128 16-column tiles)
+// split into slices of at least two k steps until about 256 workgroups run (the partials are
+// then summed with the bias and the activation); the others follow long_k_splits.
 inline int fwd_splits(int M, int N, int K) {
     const int ksteps = (K + 15) / 16;
     const int wgs = ((M + 63) / 64) * ((N + 15) / 16);
-    if (wgs >= 128) return 1;
-    return std::max(1, std::min(ksteps / 2, (256 + wgs - 1) / wgs));
+    if (wgs < 128) return std::max(1, std::min(ksteps / 2, (256 + wgs - 1) / wgs));
+    return long_k_splits(M, N, K);
 }
 
 struct EpiPartial {
@@ -456,7 +473,31 @@ inline size_t wgrad_part_floats(const ConvGeo& g) {
     return static_cast<size_t>(gemm_slices(Mo, wgrad_splits(g))) * g.Co * 9 * g.Cs;
 }
 
-// wpart: scratch of at least wgrad_part_floats(g) floats.
+// Input gradient of layer g (an Mi x Ci x 9Cos product): its split, and the floats of its
+// partials ([slice][Mi][Cs]; 0 without a split)
+inline int dgrad_splits(const ConvGeo& g) { return long_k_splits(g.N * g.Hi * g.Wi, g.Ci, 9 * g.Cos); }
+inline size_t dgrad_part_floats(const ConvGeo& g) {
+    const int sk = dgrad_splits(g);
+    if (sk <= 1) return 0;
+    return static_cast<size_t>(gemm_slices(9 * g.Cos, sk)) * g.N * g.Hi * g.Wi * g.Cs;
+}
+
+// scratch a layer's backward needs for its split-K partials (weight and input gradients,
+// used one after the other)
+inline size_t bwd_part_floats(const ConvGeo& g) { return std::max(wgrad_part_floats(g), dgrad_part_floats(g)); }
+
+// out[i] (= or +=) sum over the slices of part[z][i], in slice order, for the M x C input
+// gradient of a split convolution
+__global__ void __launch_bounds__(256) dgrad_reduce_kernel(const float* __restrict__ part, int slices,
+                                                           float* __restrict__ out, int64_t n, int accumulate) {
+    const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+    if (i >= n) return;
+    float v = 0.f;
+    for (int z = 0; z < slices; ++z) v += part[z * n + i];
+    out[i] = accumulate ? out[i] + v : v;
+}
+
+// wpart: scratch of at least bwd_part_floats(g) floats.
 template <class DZ>
 void conv_backward(const ConvGeo& g, DZ dz, const uint16_t* in, const float* w, float* dw, float* db,
                    float* da_in, int accumulate_da, float* wpart, hipStream_t st) {
@@ -475,8 +516,16 @@ void conv_backward(const ConvGeo& g, DZ dz, const uint16_t* in, const float* w, 
     hipLaunchKernelGGL(bias_sum_kernel, dim3(1), dim3(256), 0, st, wpart, groups, g.Co, db);
     if (da_in) {
         const int Mi = g.N * g.Hi * g.Wi;
-        gemm_nt(g.Ci, DgradA<DZ>{dz, g}, DgradB{w, g}, EpiStore{da_in, Mi, g.Cs, accumulate_da}, Mi,
-                9 * g.Cos, 1, st);
+        const int skd = dgrad_splits(g);
+        if (skd > 1) {   // wpart is free again once the bias partials are summed
+            gemm<1>(DgradA<DZ>{dz, g}, DgradB{w, g}, EpiPartial{wpart, Mi, g.Cs}, Mi, g.Ci, 9 * g.Cos, skd, st);
+            const int64_t n = static_cast<int64_t>(Mi) * g.Cs;
+            hipLaunchKernelGGL(dgrad_reduce_kernel, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, st,
+                               wpart, gemm_slices(9 * g.Cos, skd), da_in, n, accumulate_da);
+        } else {
+            gemm_nt(g.Ci, DgradA<DZ>{dz, g}, DgradB{w, g}, EpiStore{da_in, Mi, g.Cs, accumulate_da}, Mi,
+                    9 * g.Cos, 1, st);
+        }
     }
 }
 

@@ -578,7 +578,7 @@ size_t carve_pws(char* base, int B, int total, PWS* w) {
     }
     w->skp = reinterpret_cast<float*>(take(sizeof(float) * nsk));
     size_t nwp = 0;
-    for (int i = 0; i < kBlocks; ++i) nwp = std::max(nwp, wgrad_part_floats(pconv_geo(i, B)));
+    for (int i = 0; i < kBlocks; ++i) nwp = std::max(nwp, bwd_part_floats(pconv_geo(i, B)));
     w->wpart = reinterpret_cast<float*>(take(sizeof(float) * nwp));
     return off;
 }
