@@ -95,8 +95,17 @@ __global__ void gap_kernel(const uint16_t* __restrict__ a, float* __restrict__ g
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= B * C) return;
     const int n = i / C, c = i - (i / C) * C;
+    const uint16_t* src = a + static_cast<int64_t>(n) * HW * C + c;
     float s = 0.f;
-    for (int p = 0; p < HW; ++p) s += bf2f(a[(static_cast<int64_t>(n) * HW + p) * C + c]);
+    int p = 0;
+    for (; p + 8 <= HW; p += 8) {      // eight loads in flight, added in pixel order
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = bf2f(src[static_cast<int64_t>(p + u) * C]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) s += v[u];
+    }
+    for (; p < HW; ++p) s += bf2f(src[static_cast<int64_t>(p) * C]);
     g[i] = s / static_cast<float>(HW);
 }
 
@@ -166,8 +175,17 @@ __global__ void fc_dgrad_kernel(const float* __restrict__ dout, const float* __r
 
 __global__ void fc_dgrad_reduce_kernel(const float* __restrict__ part, float* __restrict__ dg, int nch) {
     const int n = blockIdx.x, c = threadIdx.x;
+    const float* src = part + static_cast<int64_t>(n) * nch * kGap + c;
     float acc = 0.f;
-    for (int k = 0; k < nch; ++k) acc += part[(static_cast<int64_t>(n) * nch + k) * kGap + c];
+    int k = 0;
+    for (; k + 8 <= nch; k += 8) {     // eight loads in flight, added in chunk order
+        float v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = src[static_cast<int64_t>(k + u) * kGap];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; k < nch; ++k) acc += src[static_cast<int64_t>(k) * kGap];
     dg[n * kGap + c] = acc;
 }
 

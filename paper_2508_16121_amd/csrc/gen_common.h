@@ -404,6 +404,43 @@ __global__ void __launch_bounds__(256) wgrad_reduce_kernel(const float* __restri
     if (lane == 0 && ci < Ci) dw[(static_cast<int64_t>(co) * 9 + tap) * Ci + ci] = acc;
 }
 
+// The same sums for split-K partials of up to kWgradColumnsMax slices: a workgroup of 64 x nw
+// threads takes 64 consecutive entries (consecutive addresses in every slice), wave w adds
+// the slices [w S / nw, (w + 1) S / nw) of its lane's entry in order with eight loads in
+// flight, and the waves' sums are added in wave order.
+constexpr int kWgradColumnsMax = 512;
+__global__ void __launch_bounds__(1024) wgrad_reduce_cols_kernel(const float* __restrict__ part, int slices,
+                                                                float* __restrict__ dw, int Co, int Ci, int Cs) {
+    __shared__ float red[16][kWave];
+    const int N = 9 * Cs;
+    const int64_t total = static_cast<int64_t>(Co) * N;
+    const int lane = threadIdx.x & (kWave - 1), wave = threadIdx.x / kWave, nw = blockDim.x / kWave;
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * kWave + lane;
+    const int z0 = static_cast<int>(static_cast<int64_t>(slices) * wave / nw);
+    const int z1 = static_cast<int>(static_cast<int64_t>(slices) * (wave + 1) / nw);
+    float acc = 0.f;
+    if (i < total) {
+        int z = z0;
+        for (; z + 8 <= z1; z += 8) {
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = part[(z + u) * total + i];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; z < z1; ++z) acc += part[z * total + i];
+    }
+    red[wave][lane] = acc;
+    __syncthreads();
+    if (wave == 0 && i < total) {
+        float sum = red[0][lane];
+        for (int w = 1; w < nw; ++w) sum += red[w][lane];
+        const int co = static_cast<int>(i / N), n = static_cast<int>(i - static_cast<int64_t>(co) * N);
+        const int tap = n / Cs, ci = n - tap * Cs;
+        if (ci < Ci) dw[(static_cast<int64_t>(co) * 9 + tap) * Ci + ci] = sum;
+    }
+}
+
 __global__ void zero_f32_kernel(float* p, int64_t n) {
     for (int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x; i < n;
          i += static_cast<int64_t>(gridDim.x) * blockDim.x)
@@ -505,8 +542,15 @@ void conv_backward(const ConvGeo& g, DZ dz, const uint16_t* in, const float* w, 
     const int N = 9 * g.Cs;
     const int sk = wgrad_splits(g);
     gemm<4>(WgradA<DZ>{dz, g}, WgradB{in, g}, EpiPartial{wpart, g.Co, N}, g.Co, N, Mo, sk, st);
-    hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((g.Co * N + 3) / 4), dim3(256), 0, st, wpart,
-                       gemm_slices(Mo, sk), dw, g.Co, g.Ci, g.Cs);
+    const int slices = gemm_slices(Mo, sk);
+    if (slices <= kWgradColumnsMax) {   // one lane per weight, waves over the slices
+        const int nw = std::min(16, std::max(1, (slices + 31) / 32));
+        hipLaunchKernelGGL(wgrad_reduce_cols_kernel, dim3((g.Co * N + kWave - 1) / kWave), dim3(kWave * nw), 0, st,
+                           wpart, slices, dw, g.Co, g.Ci, g.Cs);
+    } else {                            // one wave per weight, lanes over the slices
+        hipLaunchKernelGGL(wgrad_reduce_kernel, dim3((g.Co * N + 3) / 4), dim3(256), 0, st, wpart, slices, dw, g.Co,
+                           g.Ci, g.Cs);
+    }
     // the weight-gradient partials are consumed by now: wpart takes the bias partials
     const int px_per_wg = bias_lanes(g.Co) * kBiasPx;
     const int groups = static_cast<int>(std::max<size_t>(
