@@ -354,8 +354,17 @@ __global__ void __launch_bounds__(256) bias_grad_kernel(DZ dz, float* __restrict
     const int chunk = nl * kBiasPx;
     float acc = 0.f;
     if (lane < nl && t < Co * nl)
-        for (int m0 = blockIdx.x * chunk; m0 < M; m0 += gridDim.x * chunk)
-            for (int m = m0 + lane; m < min(M, m0 + chunk); m += nl) acc += dz(m, co);
+        for (int m0 = blockIdx.x * chunk; m0 < M; m0 += gridDim.x * chunk) {
+            // the chunk's kBiasPx pixels of this lane: all loads in flight, then added in order
+            float v[kBiasPx];
+#pragma unroll
+            for (int q = 0; q < kBiasPx; ++q) {
+                const int m = m0 + lane + q * nl;
+                v[q] = m < M ? dz(m, co) : 0.f;
+            }
+#pragma unroll
+            for (int q = 0; q < kBiasPx; ++q) acc += v[q];
+        }
     red[t] = acc;
     __syncthreads();
     if (t < Co) {
