@@ -595,24 +595,21 @@ __global__ void __launch_bounds__(512) apply_bwd_kernel(BwdDev P) {
         }
     }
     if (P.want_db) {
+        // the workgroup's dbias: lanes, then waves in order; one value per channel leaves the
+        // workgroup (a global atomic per wave would queue on the image's three addresses)
         __shared__ float dbw[3][1024 / kWave];
 #pragma unroll
         for (int c = 0; c < 3; ++c) {
             float v = dbsum[c];
             for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-            if (P.dbpart) {
-                if ((threadIdx.x & 63) == 0) dbw[c][wave] = v;
-            } else if ((threadIdx.x & 63) == 0) {
-                gbl_add(a.dbias + 3 * b + c, v);
-            }
+            if ((threadIdx.x & 63) == 0) dbw[c][wave] = v;
         }
-        if (P.dbpart) {
-            __syncthreads();
-            if (threadIdx.x < 3) {      // the waves' sums in wave order
-                float v = 0.f;
-                for (int i = 0; i < nw; ++i) v += dbw[threadIdx.x][i];
-                P.dbpart[3 * lb + threadIdx.x] = v;
-            }
+        __syncthreads();
+        if (threadIdx.x < 3) {
+            float v = 0.f;
+            for (int i = 0; i < nw; ++i) v += dbw[threadIdx.x][i];
+            if (P.dbpart) P.dbpart[3 * lb + threadIdx.x] = v;
+            else gbl_add(a.dbias + 3 * b + threadIdx.x, v);
         }
     }
     if (LOSS) {
