@@ -150,6 +150,12 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
     }
     wave_sync();
 
+    // a one-column map (a scalar weight per LUT, as in the paper's model): every lane's terms
+    // land on column 0, so the wave adds them up first and one lane adds the nine sums
+    const bool one_col = FASTMAP && w == 1;
+    int msum[9];
+#pragma unroll
+    for (int l = 0; l < 9; ++l) msum[l] = 0;
     if (x0 < W) {
         float dx[3][4];
         const AxisMap& ax = G.ax;
@@ -294,17 +300,30 @@ __device__ __forceinline__ void bwd_tile(const BwdDev& P, const BwdGeo& G, int b
             }
         }
         if (FASTMAP && P.want_dmap) {
+            if (one_col) {
 #pragma unroll
-            for (int l = 0; l < 9; ++l) {
-                lds_addi(dstage + j0 * kBwdStride + l, fixc<EXACT>(A0[l], sM));
-                lds_addi(dstage + j1 * kBwdStride + l, fixc<EXACT>(A1[l], sM));
-                lds_addi(dstage + j2 * kBwdStride + l, fixc<EXACT>(A2[l], sM));
+                for (int l = 0; l < 9; ++l) msum[l] = fixc<EXACT>(A0[l] + A1[l] + A2[l], sM);
+            } else {
+#pragma unroll
+                for (int l = 0; l < 9; ++l) {
+                    lds_addi(dstage + j0 * kBwdStride + l, fixc<EXACT>(A0[l], sM));
+                    lds_addi(dstage + j1 * kBwdStride + l, fixc<EXACT>(A1[l], sM));
+                    lds_addi(dstage + j2 * kBwdStride + l, fixc<EXACT>(A2[l], sM));
+                }
             }
         }
         if (P.want_dx) {
             IO* dxo = reinterpret_cast<IO*>(a.dx) + img;
 #pragma unroll
             for (int c = 0; c < 3; ++c) store_px4<IO, VEC>(dxo + c * plane, x0, W, dx[c]);
+        }
+    }
+    if (one_col && P.want_dmap) {   // integer sums: exact in any order
+#pragma unroll
+        for (int l = 0; l < 9; ++l) {
+            int v = msum[l];
+            for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+            if (lane == 0) lds_addi(dstage + l, v);
         }
     }
     wave_sync();

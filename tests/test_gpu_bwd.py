@@ -67,6 +67,8 @@ def dx_bar(G, m, U, s, V, D):
     (3, 64, 64, 17, 4, 8, 8),      # batch of three
     (1, 1, 1, 9, 2, 1, 1),         # single pixel
     (1, 16, 515, 33, 8, 1, 65),    # one map row
+    (2, 48, 530, 33, 8, 1, 1),     # a 1 x 1 map (scalar LUT weights): each wave sums its lanes' terms
+    (1, 40, 300, 17, 4, 5, 1),     # one map column over several rows
 ])
 def test_backward_parity_small(svd, shape):
     B, H, W, D, R, h, w = shape
