@@ -270,7 +270,15 @@ __global__ void __launch_bounds__(256) grid_reduce_kernel(const float* __restric
     float dot = 0.f;
     for (int e = threadIdx.x; e < Ds * Ds; e += blockDim.x) {
         float acc = 0.f;
-        for (int q = 0; q < gpi; ++q) acc += src[static_cast<size_t>(q) * nf + e];
+        int q = 0;
+        for (; q + 8 <= gpi; q += 8) {     // eight partials in flight, added in workgroup order
+            float v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) v[u] = src[static_cast<size_t>(q + u) * nf + e];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) acc += v[u];
+        }
+        for (; q < gpi; ++q) acc += src[static_cast<size_t>(q) * nf + e];
         dg[e] = w * acc;
         dot = fmaf(g[e], acc, dot);
     }

@@ -330,6 +330,7 @@ __global__ void hid_fwd_kernel(const float* __restrict__ f, Heads hs, float* __r
     const float* w = hs.w1[h] + k * kFeat;
     const float* fb = f + b * kFeat;
     float acc = hs.b1[h][k];
+#pragma unroll 16
     for (int c = 0; c < kFeat; ++c) acc = fmaf(fb[c], w[c], acc);
     hid[b * kHeads * kHid + h * kHid + k] = acc;
 }
