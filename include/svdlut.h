@@ -266,7 +266,7 @@ typedef struct {
  * svdlut_plan — one persistent launch over every pixel tile of a batch of uneven images,
  * captured once into a HIP graph and replayed.  Tiles are ordered image-major so that a
  * workgroup rebuilds a given image's LUTs at most once.  Creating a plan uploads the
- * descriptors and the tile prefix table to device memory owned by the plan (the only
+ * descriptors and the tile prefix tables (one per tile width) to device memory owned by the plan (the only
  * allocation on this path) and picks tile and grid shapes from the autotuner's cache
  * (or the built-in default).  Launching with other buffer addresses than the previous
  * launch updates the graph's kernel arguments in place before the replay.
